@@ -1,0 +1,433 @@
+"""Pins of the oracle's Newton, Armijo-backtracking and dogleg solvers.
+
+Each check ties the oracle to something other than itself: closed-form roots
+of separable instances (Cardano for the cubic, bisection for tanh), brute-force
+root enumeration for N = 1 and 2, MINPACK (scipy.optimize.fsolve) on instances
+with a unique root, and the invariants the paper's definitions imply
+(Sec. 2.1 stopping test, Sec. 2.2.1 sufficient decrease, Sec. 2.2.2 trust
+region and dogleg), plus the paper's Rosenbrock claim and worked examples.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.optimize
+
+import oracle
+from paper_2403_16341_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALGS = [oracle.NEWTON, oracle.ARMIJO, oracle.DOGLEG]
+
+
+def _solve_batch(b, **kw):
+    return oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off,
+                              b.abstol, b.maxiters, **kw)
+
+
+def _np_residual(family, p, u):
+    n = u.size
+    if family == oracle.CUBIC:
+        return p[: n * n].reshape(n, n) @ u + 0.1 * u ** 3 - p[n * n: n * n + n]
+    if family == oracle.TANH:
+        return p[: n * n].reshape(n, n) @ np.tanh(u) + p[n * n + n] * u - p[n * n: n * n + n]
+    if family == oracle.ROSENBROCK:
+        return np.concatenate([[1 - u[0]], 10 * (u[1:] - u[:-1] ** 2)])
+    a, b_, c = p
+    return np.array([(u[0] + a) * (u[1] ** 3 - b_) + c, np.sin(u[1] * np.exp(u[0]) - 1)])
+
+
+def _cardano_root(a, b):
+    """Real root of 0.1 u^3 + a u - b = 0 for a > 0, i.e. t^3 + P t + Q = 0 with
+    P = 10 a, Q = -10 b: t = -2 sqrt(P/3) sinh(asinh((3Q/2P) sqrt(3/P)) / 3)."""
+    mpmath.mp.dps = 40
+    P, Q = 10 * mpmath.mpf(a), -10 * mpmath.mpf(b)
+    return float(-2 * mpmath.sqrt(P / 3) * mpmath.sinh(mpmath.asinh((3 * Q / (2 * P)) * mpmath.sqrt(3 / P)) / 3))
+
+
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("n", [1, 4, 8])
+def test_separable_cubic_closed_form(alg, n):
+    b = inputs.separable_cubic(40, n, seed=11 + n, alg=alg)
+    r = _solve_batch(b)
+    assert (r["retcode"] == oracle.RC_SUCCESS).all()
+    for s in range(b.M):
+        _, _, _, p, _ = b.system(s)
+        a = np.diag(p[: n * n].reshape(n, n))
+        rhs = p[n * n:]
+        ref = np.array([_cardano_root(a[i], rhs[i]) for i in range(n)])
+        u = r["u"][b.u_off[s]:b.u_off[s + 1]]
+        assert np.abs(u - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def _bisect_scalar(h, lo, hi):
+    flo = h(lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        fm = h(mid)
+        if (fm < 0) == (flo < 0):
+            lo, flo = mid, fm
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_separable_tanh_bisection(alg):
+    n = 6
+    b = inputs.separable_tanh(40, n, seed=21, alg=alg)
+    r = _solve_batch(b)
+    assert (r["retcode"] == oracle.RC_SUCCESS).mean() > 0.9
+    for s in range(b.M):
+        if r["retcode"][s] != oracle.RC_SUCCESS:
+            continue
+        _, _, _, p, _ = b.system(s)
+        a = np.diag(p[: n * n].reshape(n, n))
+        rhs, beta = p[n * n: n * n + n], p[-1]
+        u = r["u"][b.u_off[s]:b.u_off[s + 1]]
+        for i in range(n):
+            B = (abs(rhs[i]) + abs(a[i])) / beta + 1.0
+            root = _bisect_scalar(lambda x: a[i] * math.tanh(x) + beta * x - rhs[i], -B, B)
+            assert abs(u[i] - root) <= 1e-10
+
+
+def _all_roots_scalar(h, B, grid=20001):
+    xs = np.linspace(-B, B, grid)
+    hs = np.array([h(x) for x in xs])
+    roots = []
+    for i in range(grid - 1):
+        if hs[i] == 0:
+            roots.append(xs[i])
+        elif (hs[i] < 0) != (hs[i + 1] < 0):
+            roots.append(_bisect_scalar(h, xs[i], xs[i + 1]))
+    return roots
+
+
+def test_n1_brute_force_tanh_every_success_is_an_enumerated_root():
+    rng = np.random.default_rng(31)
+    for trial in range(30):
+        a = rng.uniform(-1.5, 1.5)           # a < -beta gives up to three roots
+        beta = rng.uniform(0.05, 0.5)
+        bb = rng.uniform(-1, 1)
+        p = np.array([a, bb, beta])
+        B = (abs(bb) + abs(a)) / beta        # every root has |u| <= B since |tanh| <= 1
+        roots = _all_roots_scalar(lambda x: a * math.tanh(x) + beta * x - bb, B * 1.01 + 1e-3)
+        assert roots
+        for alg in ALGS:
+            for u0 in np.linspace(-4, 4, 5):
+                r = oracle.solve_one(oracle.TANH, alg, p, [u0], abstol=1e-12, maxiters=200)
+                if r["retcode"] == oracle.RC_SUCCESS:
+                    assert min(abs(r["u"][0] - z) for z in roots) <= 1e-9
+
+
+def test_n2_brute_force_tanh_every_success_is_an_enumerated_root():
+    """For N = 2 the first equation gives tanh(u2) in closed form as a function
+    of u1, which leaves a scalar equation in u1; its sign changes over the
+    a-priori box |u_i| <= (|b_i| + sum_j |A_ij|)/beta enumerate every root.
+    Instances keep beta >= 0.3 and |A_12| >= 0.25 so that the scan is well
+    conditioned (roots on saturated box corners are covered by the
+    Kantorovich test below instead)."""
+    rng = np.random.default_rng(32)
+    done = 0
+    while done < 12:
+        A = rng.standard_normal((2, 2)) / math.sqrt(2)
+        bb = rng.uniform(-1, 1, 2)
+        beta = rng.uniform(0.3, 0.5)
+        if abs(A[0, 1]) < 0.25:
+            continue
+        done += 1
+        trial = done
+        p = np.concatenate([A.ravel(), bb, [beta]])
+        # the box bound is attained when both tanh saturate: scan a hair wider
+        B = (np.abs(bb) + np.abs(A).sum(axis=1)) / beta * (1 + 1e-3) + 1e-6
+        t2max = math.tanh(B[1])
+
+        def t2_of(u1):
+            return (bb[0] - beta * u1 - A[0, 0] * np.tanh(u1)) / A[0, 1]
+
+        def g(u1):
+            t2 = t2_of(u1)
+            return A[1, 0] * np.tanh(u1) + A[1, 1] * t2 + beta * np.arctanh(t2) - bb[1]
+
+        # u2 = atanh(t2) is steep where |t2| -> 1: refine the grid there so that
+        # no pair of close roots hides inside one cell.
+        xs = np.linspace(-B[0], B[0], 40001)
+        t2 = np.abs(t2_of(xs))
+        cells = []
+        for i in range(xs.size - 1):
+            if t2[i] < t2max or t2[i + 1] < t2max:
+                fine = 2000 if max(t2[i], t2[i + 1]) > 0.99 else 1
+                cells.append(np.linspace(xs[i], xs[i + 1], fine + 1))
+        roots = []
+        for c in cells:
+            ok = np.abs(t2_of(c)) < t2max
+            with np.errstate(invalid="ignore"):
+                gv = np.where(ok, g(np.where(ok, c, 0.0)), np.nan)
+            for i in range(c.size - 1):
+                if ok[i] and ok[i + 1] and (gv[i] < 0) != (gv[i + 1] < 0):
+                    u1 = _bisect_scalar(lambda x: float(g(x)), c[i], c[i + 1])
+                    roots.append(np.array([u1, math.atanh(t2_of(u1))]))
+        assert roots, "a coercive tanh system always has a root"
+        for alg in ALGS:
+            for u0 in rng.uniform(-4, 4, (6, 2)):
+                r = oracle.solve_one(oracle.TANH, alg, p, u0, abstol=1e-12, maxiters=200)
+                if r["retcode"] == oracle.RC_SUCCESS:
+                    d = min(np.abs(r["u"] - z).max() for z in roots)
+                    assert d <= 1e-8, (trial, alg, u0, r["u"], roots)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_unique_root_cubic_agrees_with_minpack(k):
+    """Cubic with sym(A) positive definite is strongly monotone: one root, which
+    MINPACK's hybrd (scipy.optimize.fsolve) must also find."""
+    b = inputs.config(k, M=60)
+    r = _solve_batch(b)
+    assert (r["retcode"] == oracle.RC_SUCCESS).all()
+    for s in range(b.M):
+        f, n, _, p, u0 = b.system(s)
+        A = p[: n * n].reshape(n, n)
+        assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+        ref = scipy.optimize.fsolve(lambda x: _np_residual(f, p, x), u0, xtol=1e-14)
+        u = r["u"][b.u_off[s]:b.u_off[s + 1]]
+        assert np.abs(u - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_success_invariant_recomputed_in_numpy(k):
+    b = inputs.config(k, M=300)
+    r = _solve_batch(b)
+    for s in range(b.M):
+        if r["retcode"][s] != oracle.RC_SUCCESS:
+            continue
+        f, n, _, p, _ = b.system(s)
+        u = r["u"][b.u_off[s]:b.u_off[s + 1]]
+        Fn = np.abs(_np_residual(f, p, u)).max()
+        assert Fn <= b.abstol * (1 + 1e-6) + 1e-14
+        assert r["fnorm_inf"][s] <= b.abstol
+
+
+def test_newton_quadratic_tail():
+    """Near a simple root Newton's error squares each step (Sec. 2.1, fast local
+    convergence): ||F_{k+1}|| <= K ||F_k||^2 with a bounded K."""
+    b = inputs.config(2, M=200)
+    worst = 0.0
+    for s in range(b.M):
+        f, n, _, p, u0 = b.system(s)
+        r = oracle.solve_one(f, oracle.NEWTON, p, u0, abstol=1e-300, maxiters=12, trace_cap=32)
+        fi = r["trace"]["finf"]
+        checked = 0
+        for k in range(len(fi) - 1):
+            if 1e-9 < fi[k] < 1e-3 and fi[k + 1] > 1e-13:
+                worst = max(worst, fi[k + 1] / fi[k] ** 2)
+                checked += 1
+        # the last informative step must show the quadratic rate
+    assert 0 < worst <= 50.0
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_armijo_sufficient_decrease_invariant(k):
+    b = inputs.config(k, M=80)
+    opts = oracle.default_opts()
+    for s in range(b.M):
+        f, n, _, p, u0 = b.system(s)
+        r = oracle.solve_one(f, oracle.ARMIJO, p, u0, abstol=1e-10, maxiters=100, trace_cap=128)
+        t = r["trace"]
+        for i in range(len(t["k"])):
+            if t["accepted"][i] == 1:
+                alpha = t["alpha"][i]
+                assert alpha > 0 and math.log2(alpha) == round(math.log2(alpha))
+                assert t["merit"][i] <= (1 - 2 * opts["armijo_c"] * alpha) * t["merit_before"][i]
+                assert t["merit"][i] < t["merit_before"][i]
+            else:
+                assert r["retcode"] == oracle.RC_LINESEARCH_FAILED and i == len(t["k"]) - 1
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_dogleg_invariants(k):
+    b = inputs.config(k, M=60)
+    for s in range(b.M):
+        f, n, _, p, u0 = b.system(s)
+        r = oracle.solve_one(f, oracle.DOGLEG, p, u0, abstol=1e-10, maxiters=100, trace_cap=128)
+        t = r["trace"]
+        merit_prev = None
+        accepted_before_last = 0
+        for i in range(len(t["k"])):
+            D, step, kind = t["delta"][i], t["step"][i], t["kind"][i]
+            assert step <= D * (1 + 1e-12)
+            # Newton step iff it fits in the region
+            assert (kind == 0) == (t["newton_norm"][i] <= D)
+            if kind != 3:
+                # Cauchy decrease: pred >= ||g|| min(Delta, ||g||^2/||Jg||^2 * ||g||)
+                gn, tc = t["gnorm"][i], t["cauchy"][i]
+                slack = 64 * np.finfo(float).eps * t["merit_before"][i]   # cancellation in pred
+                assert t["pred"][i] >= gn * min(D, tc * gn) * (1 - 1e-9) - slack
+            if t["accepted"][i] == 1:
+                assert t["merit"][i] < t["merit_before"][i]
+                if merit_prev is not None:
+                    assert t["merit"][i] <= merit_prev
+                merit_prev = t["merit"][i]
+                if i < len(t["k"]) - 1:
+                    accepted_before_last += 1
+            else:
+                # a rejected trial shrinks the radius to a quarter of the step
+                if i + 1 < len(t["k"]):
+                    assert t["delta"][i + 1] == 0.25 * step
+        assert r["njev"] == 1 + accepted_before_last or r["retcode"] == oracle.RC_SINGULAR
+        assert r["nfev"] == r["iters"] + 1
+
+
+def test_armijo_with_full_steps_equals_newton_bitwise():
+    """When every first trial (alpha = 1) is accepted, backtracking Newton takes
+    exactly the Newton iterates."""
+    b = inputs.config(2, M=100)
+    rn = _solve_batch(b.__class__(**{**b.__dict__, "alg": np.zeros_like(b.alg)}))
+    ra = _solve_batch(b)
+    full = ra["nfev"] == ra["iters"] + 1          # one trial per iteration
+    assert full.mean() > 0.9
+    for s in np.nonzero(full)[0]:
+        sl = slice(b.u_off[s], b.u_off[s + 1])
+        assert np.array_equal(rn["u"][sl], ra["u"][sl])
+        assert rn["iters"][s] == ra["iters"][s] and rn["retcode"][s] == ra["retcode"][s]
+
+
+def test_dogleg_with_huge_radius_equals_newton_bitwise():
+    b = inputs.config(1, M=100)
+    for s in range(b.M):
+        f, n, _, p, u0 = b.system(s)
+        rn = oracle.solve_one(f, oracle.NEWTON, p, u0, abstol=1e-10, maxiters=50)
+        rd = oracle.solve_one(f, oracle.DOGLEG, p, u0, abstol=1e-10, maxiters=50,
+                              opts=dict(tr_delta0=1e300), trace_cap=64)
+        if (rd["trace"]["accepted"] == 1).all():
+            assert np.array_equal(rn["u"], rd["u"]) and rn["iters"] == rd["iters"]
+
+
+def test_rosenbrock_paper_claim_and_root():
+    g = json.load(open(os.path.join(GOLDEN, "rosenbrock_n10.json")))
+    u0, tol, mi = np.array(g["u0"]), g["abstol"], g["maxiters"]
+    root = np.array(g["known_root"])
+    # plain Newton-Raphson does not converge from this start
+    rn = oracle.solve_one(oracle.ROSENBROCK, oracle.NEWTON, np.zeros(0), u0, abstol=tol, maxiters=mi)
+    assert rn["retcode"] != oracle.RC_SUCCESS
+    # backtracking (halving) with enough halvings converges to the unique root
+    ra = oracle.solve_one(oracle.ROSENBROCK, oracle.ARMIJO, np.zeros(0), u0, abstol=tol, maxiters=mi,
+                          opts=dict(armijo_max_halvings=30))
+    assert ra["retcode"] == oracle.RC_SUCCESS
+    assert np.abs(ra["u"] - root).max() <= 1e-8
+    # with the default cap of 10 halvings the first line search already fails
+    r10 = oracle.solve_one(oracle.ROSENBROCK, oracle.ARMIJO, np.zeros(0), u0, abstol=tol, maxiters=mi)
+    assert r10["retcode"] == oracle.RC_LINESEARCH_FAILED and r10["iters"] == 1
+    rd = oracle.solve_one(oracle.ROSENBROCK, oracle.DOGLEG, np.zeros(0), u0, abstol=tol, maxiters=mi)
+    assert rd["retcode"] == oracle.RC_SUCCESS
+    assert np.abs(rd["u"] - root).max() <= 1e-8
+
+
+def test_paper_example_success_is_a_root():
+    g = json.load(open(os.path.join(GOLDEN, "paper_example.json")))
+    p = np.array(g["p"])
+    reached = 0
+    for alg in ALGS:
+        r = oracle.solve_one(oracle.PAPER, alg, p, np.array(g["u0"]), abstol=1e-10, maxiters=100)
+        if r["retcode"] == oracle.RC_SUCCESS:
+            reached += 1
+            assert np.abs(_np_residual(oracle.PAPER, p, r["u"])).max() <= 1e-10 * (1 + 1e-6)
+    assert reached >= 1
+
+
+def test_no_root_instance_never_succeeds():
+    for alg in ALGS:
+        b = inputs.no_root_tanh(30, 5, seed=41, alg=alg)
+        r = _solve_batch(b)
+        assert (r["retcode"] != oracle.RC_SUCCESS).all()
+        assert (r["fnorm_inf"] >= 1.0).all()
+
+
+def test_singular_instance():
+    for alg in ALGS:
+        b = inputs.singular_cubic(4, 3, alg=alg)
+        r = _solve_batch(b)
+        assert (r["retcode"] == oracle.RC_SINGULAR).all()
+        assert (r["iters"] == 1).all() and (r["njev"] == 1).all() and (r["nfev"] == 1).all()
+
+
+def test_edge_cases_nonfinite_maxiters_abstol():
+    b = inputs.config(1, M=4)
+    f, n, alg, p, u0 = b.system(0)
+    bad = u0.copy()
+    bad[1] = np.nan
+    for a in ALGS:
+        r = oracle.solve_one(f, a, p, bad, abstol=1e-10, maxiters=50)
+        assert r["retcode"] == oracle.RC_NONFINITE and r["iters"] == 0 and r["nfev"] == 1
+        assert r["fnorm_inf"] == np.inf
+        pbad = p.copy()
+        pbad[3] = np.inf
+        r = oracle.solve_one(f, a, pbad, u0, abstol=1e-10, maxiters=50)
+        assert r["retcode"] == oracle.RC_NONFINITE and r["iters"] == 0
+        r = oracle.solve_one(f, a, p, u0, abstol=1e-10, maxiters=0)
+        assert r["retcode"] == oracle.RC_MAXITERS and r["iters"] == 0 and r["nfev"] == 1
+        r = oracle.solve_one(f, a, p, u0, abstol=0.0, maxiters=30)
+        # abstol = 0 is met only by an exactly zero residual; otherwise the
+        # solver stops at the rounding floor by the cap, a failed line search or
+        # a collapsed region
+        assert r["retcode"] != oracle.RC_SUCCESS or r["fnorm_inf"] == 0.0
+        assert r["retcode"] in (oracle.RC_SUCCESS, oracle.RC_MAXITERS,
+                                oracle.RC_LINESEARCH_FAILED, oracle.RC_TR_COLLAPSED)
+        # a start that already satisfies the test takes no iteration
+        r0 = oracle.solve_one(f, a, p, u0, abstol=1e-10, maxiters=50)
+        r = oracle.solve_one(f, a, p, r0["u"], abstol=1e-10, maxiters=50)
+        assert r["retcode"] == oracle.RC_SUCCESS and r["iters"] == 0 and r["njev"] == 0
+
+
+def test_newton_counters():
+    b = inputs.config(1, M=50)
+    r = _solve_batch(b)
+    assert np.array_equal(r["nfev"], r["iters"] + 1)
+    assert np.array_equal(r["njev"], r["iters"])
+
+
+def test_batch_equals_one_by_one_and_threads_do_not_matter():
+    b = inputs.config(4, M=120)
+    r1 = _solve_batch(b, nthreads=1)
+    r4 = _solve_batch(b, nthreads=4)
+    for key in ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev"):
+        assert np.array_equal(r1[key], r4[key], equal_nan=True)
+    for s in range(0, b.M, 7):
+        f, n, a, p, u0 = b.system(s)
+        r = oracle.solve_one(f, a, p, u0, abstol=b.abstol, maxiters=b.maxiters)
+        assert np.array_equal(r["u"], r1["u"][b.u_off[s]:b.u_off[s + 1]])
+        assert r["retcode"] == r1["retcode"][s] and r["iters"] == r1["iters"][s]
+
+
+def test_tanh_success_is_within_kantorovich_radius_of_a_true_root():
+    """Newton-Kantorovich: with b0 = ||J(u)^-1||, eta = ||J(u)^-1 F(u)|| and L a
+    Lipschitz constant of J (|tanh''| <= 4/(3 sqrt 3) gives L = 0.77 max_i
+    sum_j |A_ij| in the inf-norm), h = b0 eta L <= 1/2 guarantees a true root
+    within 2 eta of u.  Evaluated in 40-digit mpmath, independent of the oracle."""
+    mpmath.mp.dps = 40
+    b = inputs.config(3, M=120)
+    r = _solve_batch(b)
+    succ = np.nonzero(r["retcode"] == oracle.RC_SUCCESS)[0]
+    assert succ.size > 20
+    for s in succ:
+        f, n, _, p, _ = b.system(s)
+        u = r["u"][b.u_off[s]:b.u_off[s + 1]]
+        A = mpmath.matrix(p[: n * n].reshape(n, n).tolist())
+        beta = mpmath.mpf(p[-1])
+        bb = p[n * n: n * n + n]
+        t = [mpmath.tanh(mpmath.mpf(x)) for x in u]
+        F = mpmath.matrix([mpmath.fsum(A[i, j] * t[j] for j in range(n)) + beta * u[i] - bb[i]
+                           for i in range(n)])
+        J = mpmath.matrix(n, n)
+        for i in range(n):
+            for j in range(n):
+                J[i, j] = A[i, j] * (1 - t[j] ** 2) + (beta if i == j else 0)
+        Ji = J ** -1
+        b0 = mpmath.mnorm(Ji, "inf")
+        eta = mpmath.mnorm(Ji * F, "inf")
+        L = mpmath.mpf("0.7699") * max(mpmath.fsum(abs(A[i, j]) for j in range(n)) for i in range(n))
+        assert b0 * eta * L <= 0.5
+        assert 2 * eta <= 1e-8 * max(1.0, float(mpmath.mnorm(mpmath.matrix(u.tolist()), "inf")))
