@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark: converged solves/s of the batched nonlinear solver on one MI355X.
+
+Workload (the headline): 2^20 independent systems of N = 8, cubic family
+F(u) = A u + 0.1 u^3 - b with A = 4I + 0.5G, u0 ~ U(-3, 3), Newton with Armijo
+backtracking, abstol 1e-10, maxiters 100; inputs synthetic and seeded, already
+resident in device memory.  One step = one nls_solve_batch of the whole batch
+(validation, launch, solve, result write-back) until its ticket completes.
+
+Prints one JSON line (plain FP64 form as `value`; the FP32-inner form, the
+roofline of the solver kernel and the CPU oracle baseline ride along).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
+
+
+def flops_armijo_cubic(n, iters, nfev):
+    """Per-system flop model (+,-,*,/,sqrt count 1, FMA 2): initial residual,
+    then per iteration Jacobian + LU + triangular solves, and per trial a
+    residual plus the 4N flops of forming the trial and its merit."""
+    R = 2 * n * n + 5 * n
+    J = 3 * n
+    LU = 2 * n ** 3 / 3 - n * n / 2 - n / 6
+    TRSV = 2 * n * n - n
+    trials = nfev - 1
+    return R + iters * (J + LU + TRSV) + trials * (R + 4 * n)
+
+
+def run_form(nls, ctx, db, precision, steps, warmup, with_counters=False):
+    import torch
+    out = db.alloc_results()
+    if not with_counters:
+        out["nfev"] = None
+        out["njev"] = None
+    kw = dict(count=db.M, family=db.family, n=db.n, alg=db.alg, params=db.params, u0=db.u0,
+              p_offset=db.p_offset, u_offset=db.u_offset, abstol=db.abstol, maxiters=db.maxiters,
+              precision=precision, out=out)
+    for _ in range(warmup):
+        t, _k = ctx.submit(**kw)
+        ctx.query(t, -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [ctx.submit(**kw)[0] for _ in range(steps)]
+    gpu_ms = [ctx.query(t, -1).gpu_ms for t in tickets]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return out, wall / steps, gpu_ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--systems", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
+              "(--gpus 1); multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_16341_amd import inputs, nls
+
+    b = inputs.config(2, M=args.systems)
+    M, n = b.M, 8
+    print("[bench] workload %s: %d systems, generated" % (b.name, M), file=sys.stderr, flush=True)
+    ctx = nls.Context(0)
+    db = nls.DeviceBatch(b)
+    torch.cuda.synchronize()
+
+    out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
+    rc64 = out64["retcode"].cpu().numpy()
+    conv64 = int((rc64 == 0).sum())
+    print("[bench] fp64: %.3f ms/step, kernel %.3f ms, %d converged" % (step64 * 1e3, np.mean(gpu64), conv64),
+          file=sys.stderr, flush=True)
+    out32, step32, gpu32 = run_form(nls, ctx, db, inputs.PREC_FP32_INNER, args.steps, args.warmup)
+    rc32 = out32["retcode"].cpu().numpy()
+    conv32 = int((rc32 == 0).sum())
+    print("[bench] fp32-inner: %.3f ms/step, kernel %.3f ms, %d converged"
+          % (step32 * 1e3, np.mean(gpu32), conv32), file=sys.stderr, flush=True)
+
+    # flop model from an extra (untimed) run that also returns the counters
+    cnt, _, _ = run_form(nls, ctx, db, inputs.PREC_FP64, 1, 0, with_counters=True)
+    it = cnt["iters"].cpu().numpy().astype(np.float64)
+    nf = cnt["nfev"].cpu().numpy().astype(np.float64)
+    flops = float(flops_armijo_cubic(n, it, nf).sum())
+    # error of the FP32-inner form against the FP64 form (same roots)
+    u64 = out64["u"].view(M, n)
+    u32 = out32["u"].view(M, n)
+    rel = ((u32 - u64).abs().amax(dim=1) / u64.abs().amax(dim=1).clamp_min(1e-300)).cpu().numpy()
+
+    kernel_ms = float(np.mean(gpu64))
+    bytes_per_system = 8 * (n * n + n) + 8 * n + 8 * n + 8 + 4 + 4  # A, b, u0 in; u, ||F||, iters, rc out
+    achieved = bytes_per_system * M / (kernel_ms * 1e-3) / 1e9
+    res = {
+        "metric": "converged solves/s, N=8 1M batch, FP64 vs FP32-inner; serving p50/p99 latency",
+        "value": conv64 / step64,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cubic N=8, 2^20 systems, Newton+Armijo (c=1e-4, halving, <=10), "
+                               "u0~U(-3,3), abstol 1e-10, maxiters 100",
+                   "systems": M, "n": n, "family": "cubic", "alg": "newton_armijo", "precision": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_lane<8,cubic,armijo,double>", "kernel_ms": kernel_ms,
+                     "bytes_per_system": bytes_per_system},
+        "flop_model": {"flops": flops, "tflops": flops / (kernel_ms * 1e-3) / 1e12,
+                       "fp64_vector_frac": flops / (kernel_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                       "mean_iters": float(it.mean()), "mean_trials": float((nf - 1).mean())},
+        "fp32_inner": {"value": conv32 / step32, "ms_per_step": step32 * 1e3, "kernel_ms": float(np.mean(gpu32)),
+                       "converged": conv32, "max_rel_diff_vs_fp64": float(rel.max()),
+                       "p50_rel_diff_vs_fp64": float(np.median(rel))},
+        "retcodes_fp64": np.bincount(rc64, minlength=7).tolist(),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(len(os.sched_getaffinity(0)), 16)
+        t0 = time.perf_counter()
+        r = oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off, b.abstol,
+                               b.maxiters, nthreads=cores)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": float((r["retcode"] == 0).sum()) / dt, "unit": "solves/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": "all %d systems of the workload, single-threaded FP64 oracle per "
+                                         "system on %d threads over contiguous chunks (%.2f s)" % (M, cores, dt)}
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * nls.h -- C ABI of the MI355X batched small-system nonlinear solver.
+ *
+ * Solves M independent dense systems F(u; p) = 0, u in R^n (1 <= n <= 64),
+ * in one batch on one GPU, as in the problem statement of the paper
+ * (arXiv 2403.16341, Sec. 2, eq. nonlinear-root-finding): per system a residual
+ * family, fixed parameters p (theta) and an initial guess u0; an absolute
+ * tolerance on ||F||_inf (Sec. 2.1 stopping test); an iteration cap (Sec. 4
+ * uses 1000; here a per-batch value); and an algorithm (Sec. 3 workflow: the
+ * algorithm is the second argument of solve).  Per system the library returns
+ * the final iterate u, ||F(u)||_inf, the iteration count and a return code
+ * (the solution object and its success flag, Sec. 3.3).
+ *
+ * Algorithms (Sec. 2.1 and 2.2): Newton-Raphson (eq. newton_descent),
+ * Newton-Raphson with backtracking under the Armijo sufficient-decrease test
+ * (eq. sufficient-decrease), and a trust region whose subproblem
+ * (eq. tr_subproblem) is solved by Powell's dogleg.  Jacobians come from
+ * forward-mode dual numbers (Sec. 2.4); each Newton system is solved by LU
+ * with partial pivoting (Sec. 3.2, small dense default).
+ *
+ * Conventions for every entry point:
+ *   - return value: NLS_OK (0), NLS_PENDING (1, nls_query only) or a negative
+ *     NLS_E_* code.  Numerical outcomes are never API errors: they are the
+ *     per-system return codes NLS_RC_*.
+ *   - an API error is reported before any device work is enqueued and leaves
+ *     every output buffer untouched; nls_last_error() then holds a message
+ *     (and, for a bad system, its index).
+ *   - "host" arrays are ordinary CPU memory; "payload" arrays live where
+ *     nls_batch.mem_kind says (host memory, or device memory of the context's
+ *     GPU, e.g. torch tensors' data_ptr()).
+ *   - the library never retains a pointer to caller memory beyond the call,
+ *     except device payload pointers, which it reads/writes until nls_query
+ *     reports the ticket done.
+ */
+#ifndef NLS_H
+#define NLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLS_ABI_VERSION 1
+#define NLS_NMAX 64
+
+/* ---- status codes ------------------------------------------------------ */
+#define NLS_OK 0
+#define NLS_PENDING 1
+#define NLS_E_INVALID (-1)  /* null pointer, bad size/id/option, bad offsets  */
+#define NLS_E_NOMEM (-2)    /* request can never fit the memory budget        */
+#define NLS_E_DEVICE (-3)   /* HIP error (message in nls_last_error)          */
+#define NLS_E_NOTFOUND (-4) /* unknown or already-released ticket             */
+
+/* ---- residual families (parameter packing per system, row-major A) -------
+ * CUBIC       F_i = sum_j A_ij u_j + 0.1 u_i^3 - b_i       p = [A (n*n), b (n)]
+ * TANH        F_i = sum_j A_ij tanh(u_j) + beta u_i - b_i  p = [A (n*n), b (n), beta]
+ * ROSENBROCK  F_1 = 1 - u_1, F_i = 10 (u_i - u_{i-1}^2)     p = [] (n >= 2)
+ *             (generalized Rosenbrock, Sec. 2.2.1 eq. gen_rosenbrock_function)
+ * PAPER_EXAMPLE  F_1 = (u_1 + a)(u_2^3 - b) + c,
+ *                F_2 = sin(u_2 exp(u_1) - 1)               p = [a, b, c] (n = 2)
+ *             (the workflow example of Sec. 3)                                  */
+#define NLS_FAMILY_CUBIC 0
+#define NLS_FAMILY_TANH 1
+#define NLS_FAMILY_ROSENBROCK 2
+#define NLS_FAMILY_PAPER_EXAMPLE 3
+
+/* ---- algorithms --------------------------------------------------------- */
+#define NLS_ALG_NEWTON 0        /* Sec. 2.1                                  */
+#define NLS_ALG_NEWTON_ARMIJO 1 /* Sec. 2.2.1, backtracking                  */
+#define NLS_ALG_DOGLEG 2        /* Sec. 2.2.2, trust region + Powell dogleg  */
+
+/* ---- precision forms ----------------------------------------------------
+ * FP64       : everything in binary64.
+ * FP32_INNER : Jacobian, LU factor/solve and the dogleg step algebra in
+ *              binary32; residual, norms, acceptance tests and the update
+ *              u += delta stay binary64 (Newton acts as iterative refinement). */
+#define NLS_PREC_FP64 0
+#define NLS_PREC_FP32_INNER 1
+
+#define NLS_MEM_HOST 0
+#define NLS_MEM_DEVICE 1
+
+/* ---- per-system return codes ------------------------------------------- */
+#define NLS_RC_SUCCESS 0           /* ||F(u)||_inf <= abstol                  */
+#define NLS_RC_MAXITERS 1          /* iteration cap reached                   */
+#define NLS_RC_SINGULAR 2          /* zero or non-finite LU pivot             */
+#define NLS_RC_NONFINITE 3         /* non-finite residual (Newton / start)    */
+#define NLS_RC_LINESEARCH_FAILED 4 /* no trial passed the Armijo test         */
+#define NLS_RC_TR_COLLAPSED 5      /* trust radius below collapse threshold   */
+#define NLS_RC_INVALID 6           /* never produced after validation         */
+
+/* ---- context ------------------------------------------------------------ */
+typedef struct nls_context nls_context;
+
+#define NLS_CTX_THREADSAFE 1u /* serialise calls on one context with a mutex */
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                            */
+  uint32_t flags;            /* NLS_CTX_*                                     */
+  uint64_t mem_budget_bytes; /* device bytes the library may hold; 0 = no cap */
+  void* stream;              /* hipStream_t to enqueue on; NULL = own stream  */
+} nls_context_desc;
+
+/* Algorithm options; a NULL pointer selects the defaults in brackets.
+ * Armijo (Sec. 2.2.1): trial steps alpha = rho^m, m = 0..max_halvings, accept
+ *   the first with ||F(u + alpha d)||_2^2 <= (1 - 2 c alpha) ||F(u)||_2^2
+ *   [c = 1e-4, rho = 0.5, max_halvings = 10].
+ * Trust region (Sec. 2.2.2): rho >= eta2 accept and radius = min(expand *
+ *   radius, delta_max); eta1 < rho < eta2 accept; otherwise reject and radius
+ *   = shrink * ||step||_2, failing with TR_COLLAPSED once radius < collapse *
+ *   max(1, ||u||_2) [delta0 = 1, delta_max = 1e8, eta1 = 1e-4, eta2 = 0.75,
+ *   expand = 2, shrink = 0.25, collapse = 1e-14].                             */
+typedef struct {
+  double armijo_c;
+  double armijo_rho;
+  int32_t armijo_max_halvings;
+  int32_t reserved0;
+  double tr_delta0;
+  double tr_delta_max;
+  double tr_eta1;
+  double tr_eta2;
+  double tr_expand;
+  double tr_shrink;
+  double tr_collapse;
+} nls_alg_options;
+
+/* A batch of M systems.
+ *   family/n/alg : host uint8[M] per-system descriptors, or NULL to give every
+ *                  system family_all / n_all / alg_all.
+ *   params       : payload float64, system s uses the family's P parameters at
+ *                  params[p_offset[s] .. p_offset[s] + P); p_offset: host
+ *                  int64[M+1], non-decreasing with p_offset[s+1] - p_offset[s]
+ *                  >= P (gaps allowed), or NULL = systems packed back to back.
+ *   u0           : payload float64, system s uses u0[u_offset[s] .. +n[s]);
+ *                  u_offset: host int64[M+1] with spans >= n, or NULL =
+ *                  prefix sums of n.  Result u uses the same offsets; entries
+ *                  in gaps are left untouched (device) or copied from u0 (host).
+ *   abstol >= 0, maxiters >= 0 (0 = test the start only).                     */
+typedef struct {
+  int64_t count;
+  const uint8_t* family;
+  const uint8_t* n;
+  const uint8_t* alg;
+  uint8_t family_all;
+  uint8_t n_all;
+  uint8_t alg_all;
+  uint8_t precision;    /* NLS_PREC_*                                        */
+  uint32_t mem_kind;    /* NLS_MEM_* for params, u0 and every result array  */
+  int32_t maxiters;
+  double abstol;
+  const double* params;
+  const int64_t* p_offset;
+  const double* u0;
+  const int64_t* u_offset;
+  const nls_alg_options* opts;
+} nls_batch;
+
+/* Result arrays (payload memory, caller-owned, written only by the ticket's
+ * work): u uses the same offsets as u0; the others are [M].  nfev (residual
+ * evaluations) and njev (Jacobian factorisations) may be NULL.              */
+typedef struct {
+  double* u;
+  double* fnorm_inf;
+  int32_t* iters;
+  int32_t* retcode;
+  int32_t* nfev;
+  int32_t* njev;
+} nls_results;
+
+typedef struct {
+  int32_t done;        /* 1 once every result of the ticket is written       */
+  int32_t status;      /* NLS_OK, or NLS_E_DEVICE if its work failed         */
+  double gpu_ms;       /* device time between the ticket's first and last op */
+  int64_t systems;     /* M                                                  */
+} nls_ticket_info;
+
+/* Create a context on a device.  d: non-NULL.  *out receives the handle.
+ * Errors: NLS_E_INVALID (NULL, bad device ordinal), NLS_E_DEVICE.           */
+int nls_create(const nls_context_desc* d, nls_context** out);
+
+/* Destroy a context: waits for its outstanding tickets, frees everything it
+ * owns (never the caller's buffers or stream).  NULL is a no-op.            */
+int nls_destroy(nls_context* c);
+
+/* Validate, then enqueue the solve of batch b writing r, on the context's
+ * stream; returns at once with *ticket set (device payloads) or after the
+ * inputs have been copied to the device (host payloads).  The ticket must be
+ * released by a nls_query call that reports it done.
+ * Errors: NLS_E_INVALID (see nls_validate), NLS_E_NOMEM (the batch's device
+ * footprint exceeds mem_budget_bytes), NLS_E_DEVICE.                         */
+int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, uint64_t* ticket);
+
+/* Poll (wait_ms = 0), wait up to wait_ms, or wait forever (wait_ms < 0) for
+ * a ticket.  Returns NLS_PENDING while it runs; NLS_OK once done, filling
+ * info (may be NULL) and releasing the ticket.  Errors: NLS_E_NOTFOUND.     */
+int nls_query(nls_context* c, uint64_t ticket, int32_t wait_ms, nls_ticket_info* info);
+
+/* Host-only validation of a batch (no device touched): NLS_OK or
+ * NLS_E_INVALID with *first_bad (may be NULL) = index of the first bad
+ * system, or -1 for a batch-level error.                                    */
+int nls_validate(const nls_batch* b, int64_t* first_bad);
+
+/* Message of the last error on this context (or of the last context-less
+ * call on this thread when c is NULL).  Never NULL.                         */
+const char* nls_last_error(const nls_context* c);
+
+/* Number of float64 parameters of a family at size n, or -1 if invalid.      */
+int nls_nparams(int family, int n);
+
+/* Default option values (see nls_alg_options).                              */
+void nls_default_options(nls_alg_options* o);
+
+/* NLS_ABI_VERSION of the loaded library.                                     */
+int nls_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLS_H */

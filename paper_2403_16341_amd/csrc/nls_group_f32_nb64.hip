@@ -1,0 +1,7 @@
+// Group-mapping kernels, float inner form, size bucket n <= 64.
+#include "nls_kernels.hpp"
+#include "nls_launch.h"
+#define NLS_TI float
+#define NLS_NB 64
+#define NLS_GROUP_ENTRY launch_group_f32_nb64
+#include "nls_group_dispatch.inc"

@@ -1,0 +1,560 @@
+// nls_host.cpp -- host runtime behind the C ABI of include/nls.h.
+//
+// Validation, bucketing of mixed batches by kernel mapping, device staging of
+// host payloads, launches on the context's stream, and tickets (an event per
+// batch plus the device memory to release when it completes).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "nls.h"
+#include "nls_launch.h"
+#include "nls_types.h"
+
+using namespace nls;
+
+namespace {
+
+thread_local std::string g_tls_error = "";
+
+struct Ticket {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  std::vector<void*> device_allocs;
+  int64_t systems = 0;
+  int32_t status = NLS_OK;
+  uint64_t bytes = 0;  // device bytes the ticket holds until released
+};
+
+// Size bucket of the group mapping for a system of n unknowns (n > 8).
+int group_bucket(int n) { return ((n + 7) / 8) * 8 < 16 ? 16 : ((n + 7) / 8) * 8; }
+
+bool lane_mapped(int n) { return n <= 8; }
+
+}  // namespace
+
+struct nls_context {
+  int device = 0;
+  uint32_t flags = 0;
+  uint64_t budget = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::mutex mu;
+  std::string last_error;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  uint64_t held_bytes = 0;  // device bytes held by outstanding tickets
+};
+
+namespace {
+
+int fail(nls_context* c, int code, const std::string& msg) {
+  if (c) c->last_error = msg;
+  g_tls_error = msg;
+  return code;
+}
+
+int hip_fail(nls_context* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, NLS_E_DEVICE, m);
+}
+
+int nparams_of(int family, int n) {
+  if (n < 1 || n > NLS_NMAX) return -1;
+  switch (family) {
+    case NLS_FAMILY_CUBIC: return n * n + n;
+    case NLS_FAMILY_TANH: return n * n + n + 1;
+    case NLS_FAMILY_ROSENBROCK: return n >= 2 ? 0 : -1;
+    case NLS_FAMILY_PAPER_EXAMPLE: return n == 2 ? 3 : -1;
+  }
+  return -1;
+}
+
+// A family/size pair the kernels implement (Rosenbrock has group kernels up
+// to n = 16 only).
+bool supported(int family, int n) {
+  if (nparams_of(family, n) < 0) return false;
+  if (family == NLS_FAMILY_ROSENBROCK && n > 16) return false;
+  return true;
+}
+
+void fill_defaults(nls_alg_options* o) {
+  o->armijo_c = 1e-4;
+  o->armijo_rho = 0.5;
+  o->armijo_max_halvings = 10;
+  o->reserved0 = 0;
+  o->tr_delta0 = 1.0;
+  o->tr_delta_max = 1e8;
+  o->tr_eta1 = 1e-4;
+  o->tr_eta2 = 0.75;
+  o->tr_expand = 2.0;
+  o->tr_shrink = 0.25;
+  o->tr_collapse = 1e-14;
+}
+
+std::string check_options(const nls_alg_options& o) {
+  auto ok = [](double x) { return std::isfinite(x); };
+  if (!(ok(o.armijo_c) && o.armijo_c > 0 && o.armijo_c < 0.5)) return "armijo_c must be in (0, 0.5)";
+  if (!(ok(o.armijo_rho) && o.armijo_rho > 0 && o.armijo_rho < 1)) return "armijo_rho must be in (0, 1)";
+  if (o.armijo_max_halvings < 0 || o.armijo_max_halvings > 1000) return "armijo_max_halvings must be in [0, 1000]";
+  if (!(ok(o.tr_delta0) && o.tr_delta0 > 0)) return "tr_delta0 must be > 0";
+  if (!(o.tr_delta_max >= o.tr_delta0)) return "tr_delta_max must be >= tr_delta0";
+  if (!(ok(o.tr_eta1) && ok(o.tr_eta2) && o.tr_eta1 >= 0 && o.tr_eta1 < o.tr_eta2 && o.tr_eta2 <= 1))
+    return "need 0 <= tr_eta1 < tr_eta2 <= 1";
+  if (!(ok(o.tr_expand) && o.tr_expand >= 1)) return "tr_expand must be >= 1";
+  if (!(ok(o.tr_shrink) && o.tr_shrink > 0 && o.tr_shrink < 1)) return "tr_shrink must be in (0, 1)";
+  if (!(ok(o.tr_collapse) && o.tr_collapse >= 0)) return "tr_collapse must be >= 0";
+  return "";
+}
+
+// Validation shared by nls_validate and nls_solve_batch.  Returns "" if ok.
+std::string validate(const nls_batch* b, int64_t* first_bad) {
+  if (first_bad) *first_bad = -1;
+  if (!b) return "batch is NULL";
+  if (b->count < 0) return "count must be >= 0";
+  if (b->count > (int64_t)INT32_MAX) return "count exceeds 2^31 - 1";
+  if (b->precision != NLS_PREC_FP64 && b->precision != NLS_PREC_FP32_INNER) return "unknown precision";
+  if (b->mem_kind != NLS_MEM_HOST && b->mem_kind != NLS_MEM_DEVICE) return "unknown mem_kind";
+  if (!(b->abstol >= 0.0)) return "abstol must be >= 0 (and not NaN)";
+  if (b->maxiters < 0) return "maxiters must be >= 0";
+  if (b->opts) {
+    std::string m = check_options(*b->opts);
+    if (!m.empty()) return m;
+  }
+  const int64_t M = b->count;
+  if (M == 0) return "";
+  // every system described by the scalar fields and packed back to back:
+  // one check covers the whole batch
+  const bool scalar = !b->family && !b->n && !b->alg && !b->p_offset && !b->u_offset;
+  const int64_t checked = scalar ? 1 : M;
+  int64_t ptotal = 0, utotal = 0;
+  for (int64_t s = 0; s < checked; ++s) {
+    const int fam = b->family ? b->family[s] : b->family_all;
+    const int n = b->n ? b->n[s] : b->n_all;
+    const int alg = b->alg ? b->alg[s] : b->alg_all;
+    char buf[160];
+    if (n < 1 || n > NLS_NMAX) {
+      if (first_bad) *first_bad = s;
+      std::snprintf(buf, sizeof buf, "system %lld: n = %d outside [1, 64]", (long long)s, n);
+      return buf;
+    }
+    if (fam < 0 || fam >= FAM_COUNT || !supported(fam, n)) {
+      if (first_bad) *first_bad = s;
+      std::snprintf(buf, sizeof buf, "system %lld: family %d is not defined at n = %d", (long long)s, fam, n);
+      return buf;
+    }
+    if (alg < 0 || alg >= ALG_COUNT) {
+      if (first_bad) *first_bad = s;
+      std::snprintf(buf, sizeof buf, "system %lld: unknown algorithm %d", (long long)s, alg);
+      return buf;
+    }
+    const int P = nparams_of(fam, n);
+    if (b->p_offset) {
+      if (b->p_offset[s + 1] - b->p_offset[s] < P || b->p_offset[s] < 0) {
+        if (first_bad) *first_bad = s;
+        std::snprintf(buf, sizeof buf, "system %lld: p_offset span %lld < %d parameters", (long long)s,
+                      (long long)(b->p_offset[s + 1] - b->p_offset[s]), P);
+        return buf;
+      }
+    }
+    if (b->u_offset) {
+      if (b->u_offset[s] < 0 || b->u_offset[s + 1] - b->u_offset[s] < n) {
+        if (first_bad) *first_bad = s;
+        std::snprintf(buf, sizeof buf, "system %lld: u_offset span shorter than n = %d", (long long)s, n);
+        return buf;
+      }
+    }
+    ptotal += P;
+    utotal += n;
+  }
+  (void)utotal;
+  if (!b->u0) return "u0 is NULL";
+  if (ptotal > 0 && !b->params) return "params is NULL";
+  return "";
+}
+
+std::string check_results(const nls_results* r, int64_t M) {
+  if (M == 0) return "";
+  if (!r) return "results is NULL";
+  if (!r->u || !r->fnorm_inf || !r->iters || !r->retcode) return "a required result array is NULL";
+  return "";
+}
+
+KOpts to_kopts(const nls_alg_options& o) {
+  KOpts k;
+  k.armijo_c = o.armijo_c;
+  k.armijo_rho = o.armijo_rho;
+  k.armijo_max_halvings = o.armijo_max_halvings;
+  k.pad = 0;
+  k.tr_delta0 = o.tr_delta0;
+  k.tr_delta_max = o.tr_delta_max;
+  k.tr_eta1 = o.tr_eta1;
+  k.tr_eta2 = o.tr_eta2;
+  k.tr_expand = o.tr_expand;
+  k.tr_shrink = o.tr_shrink;
+  k.tr_collapse = o.tr_collapse;
+  return k;
+}
+
+int launch(int n_or_nb, bool lane, int fam, int alg, int prec, const KArgs& a, hipStream_t st) {
+  if (lane) return prec == PREC_FP64 ? launch_lane_f64(n_or_nb, fam, alg, a, st)
+                                     : launch_lane_f32(n_or_nb, fam, alg, a, st);
+  return launch_group(prec, n_or_nb, fam, alg, a, st);
+}
+
+struct DevBuf {
+  std::vector<void*>* list;
+  uint64_t* bytes;
+  hipError_t alloc(void** p, size_t n) {
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipSuccess) {
+      list->push_back(*p);
+      *bytes += n;
+    }
+    return e;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int nls_abi_version(void) { return NLS_ABI_VERSION; }
+
+int nls_nparams(int family, int n) { return nparams_of(family, n); }
+
+void nls_default_options(nls_alg_options* o) {
+  if (o) fill_defaults(o);
+}
+
+const char* nls_last_error(const nls_context* c) {
+  if (c) return c->last_error.c_str();
+  return g_tls_error.c_str();
+}
+
+int nls_validate(const nls_batch* b, int64_t* first_bad) {
+  std::string m = validate(b, first_bad);
+  if (!m.empty()) return fail(nullptr, NLS_E_INVALID, m);
+  return NLS_OK;
+}
+
+int nls_create(const nls_context_desc* d, nls_context** out) {
+  if (!d || !out) return fail(nullptr, NLS_E_INVALID, "nls_create: NULL argument");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (d->device < 0 || d->device >= ndev) return fail(nullptr, NLS_E_INVALID, "nls_create: bad device ordinal");
+  e = hipSetDevice(d->device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  nls_context* c = new nls_context();
+  c->device = d->device;
+  c->flags = d->flags;
+  c->budget = d->mem_budget_bytes;
+  if (d->stream) {
+    c->stream = (hipStream_t)d->stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(nullptr, e, "hipStreamCreate");
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return NLS_OK;
+}
+
+static void release_ticket(Ticket& t, nls_context* c) {
+  for (void* p : t.device_allocs) hipFree(p);
+  t.device_allocs.clear();
+  if (t.start) hipEventDestroy(t.start);
+  if (t.stop) hipEventDestroy(t.stop);
+  t.start = t.stop = nullptr;
+  (void)c;
+}
+
+int nls_destroy(nls_context* c) {
+  if (!c) return NLS_OK;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& kv : c->tickets) release_ticket(kv.second, c);
+  c->tickets.clear();
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return NLS_OK;
+}
+
+int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, uint64_t* ticket) {
+  if (!c) return fail(nullptr, NLS_E_INVALID, "context is NULL");
+  std::unique_lock<std::mutex> lk(c->mu, std::defer_lock);
+  if (c->flags & NLS_CTX_THREADSAFE) lk.lock();
+  if (!ticket) return fail(c, NLS_E_INVALID, "ticket is NULL");
+  int64_t bad = -1;
+  std::string m = validate(b, &bad);
+  if (m.empty()) m = check_results(r, b->count);
+  if (!m.empty()) return fail(c, NLS_E_INVALID, m);
+
+  const int64_t M = b->count;
+  const bool dev = b->mem_kind == NLS_MEM_DEVICE;
+  nls_alg_options opts;
+  fill_defaults(&opts);
+  if (b->opts) opts = *b->opts;
+
+  // --- plan: uniform fast path or buckets ---------------------------------
+  bool uniform = true;
+  int fam0 = b->family ? (M ? b->family[0] : 0) : b->family_all;
+  int n0 = b->n ? (M ? b->n[0] : 1) : b->n_all;
+  int alg0 = b->alg ? (M ? b->alg[0] : 0) : b->alg_all;
+  const int P0 = nparams_of(fam0, n0);
+  const bool scalar = !b->family && !b->n && !b->alg && !b->p_offset && !b->u_offset;
+  for (int64_t s = 0; s < M && uniform && !scalar; ++s) {
+    const int fam = b->family ? b->family[s] : b->family_all;
+    const int n = b->n ? b->n[s] : b->n_all;
+    const int alg = b->alg ? b->alg[s] : b->alg_all;
+    if (fam != fam0 || n != n0 || alg != alg0) uniform = false;
+    if (b->p_offset && b->p_offset[s] != s * (int64_t)P0) uniform = false;
+    if (b->u_offset && b->u_offset[s] != s * (int64_t)n0) uniform = false;
+  }
+  // total payload extents
+  int64_t ptotal = 0, utotal = 0;
+  if (uniform) {
+    ptotal = M * (int64_t)P0;
+    utotal = M * (int64_t)n0;
+  } else {
+    for (int64_t s = 0; s < M; ++s) {
+      const int fam = b->family ? b->family[s] : b->family_all;
+      const int n = b->n ? b->n[s] : b->n_all;
+      const int64_t pe = (b->p_offset ? b->p_offset[s] : ptotal) + nparams_of(fam, n);
+      const int64_t ue = (b->u_offset ? b->u_offset[s] : utotal) + n;
+      if (b->p_offset) ptotal = std::max(ptotal, pe); else ptotal = pe;
+      if (b->u_offset) utotal = std::max(utotal, ue); else utotal = ue;
+    }
+  }
+
+  // device footprint of this call (library-owned memory only)
+  uint64_t need = 0;
+  if (!dev) need += (uint64_t)(ptotal + 2 * utotal + M) * 8 + (uint64_t)M * 16;
+  if (!uniform) need += (uint64_t)M * (4 + 1 + 16) + 16;
+  if (c->budget && c->held_bytes + need > c->budget) {
+    if (need > c->budget) return fail(c, NLS_E_NOMEM, "batch needs more device memory than the budget");
+    return fail(c, NLS_E_NOMEM, "budget exhausted by outstanding tickets; query them first");
+  }
+
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+
+  Ticket t;
+  t.systems = M;
+  uint64_t held = 0;
+  DevBuf db{&t.device_allocs, &held};
+  auto bail = [&](hipError_t err, const char* what) {
+    hipStreamSynchronize(c->stream);
+    release_ticket(t, c);
+    return hip_fail(c, err, what);
+  };
+  if ((e = hipEventCreate(&t.start)) != hipSuccess) return bail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&t.stop)) != hipSuccess) return bail(e, "hipEventCreate");
+  if ((e = hipEventRecord(t.start, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+
+  const double* d_params = b->params;
+  const double* d_u0 = b->u0;
+  double* d_u = r ? r->u : nullptr;
+  double* d_fn = r ? r->fnorm_inf : nullptr;
+  int32_t* d_it = r ? r->iters : nullptr;
+  int32_t* d_rc = r ? r->retcode : nullptr;
+  int32_t* d_nfev = r ? r->nfev : nullptr;
+  int32_t* d_njev = r ? r->njev : nullptr;
+
+  if (M > 0 && !dev) {
+    void *pp = nullptr, *pu0 = nullptr, *pu = nullptr, *pfn = nullptr, *pit = nullptr, *prc = nullptr;
+    void *pnf = nullptr, *pnj = nullptr;
+    if ((e = db.alloc(&pp, ptotal * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&pu0, utotal * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&pu, utotal * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&pfn, M * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&pit, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&prc, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if (r->nfev && (e = db.alloc(&pnf, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if (r->njev && (e = db.alloc(&pnj, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if (ptotal && (e = hipMemcpyAsync(pp, b->params, ptotal * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(pu0, b->u0, utotal * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    // u keeps the caller's layout: start from u0 so that gaps between systems survive
+    if ((e = hipMemcpyAsync(pu, b->u0, utotal * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    d_params = (const double*)pp;
+    d_u0 = (const double*)pu0;
+    d_u = (double*)pu;
+    d_fn = (double*)pfn;
+    d_it = (int32_t*)pit;
+    d_rc = (int32_t*)prc;
+    d_nfev = (int32_t*)pnf;
+    d_njev = (int32_t*)pnj;
+  }
+
+  KArgs base{};
+  base.params = d_params;
+  base.u0 = d_u0;
+  base.u_out = d_u;
+  base.fnorm = d_fn;
+  base.iters = d_it;
+  base.retcode = d_rc;
+  base.nfev = d_nfev;
+  base.njev = d_njev;
+  base.maxiters = b->maxiters;
+  base.abstol = b->abstol;
+  base.o = to_kopts(opts);
+
+  if (M > 0 && uniform) {
+    KArgs a = base;
+    a.count = M;
+    a.P = P0;
+    a.n = n0;
+    const bool lane = lane_mapped(n0);
+    int rcode = launch(lane ? n0 : group_bucket(n0), lane, fam0, alg0, b->precision, a, c->stream);
+    if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
+    if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
+  } else if (M > 0) {
+    // Bucket by (mapping, size bucket, family, algorithm); one launch per bucket.
+    std::map<int64_t, std::vector<int32_t>> buckets;
+    std::vector<int64_t> poff(M + 1), uoff(M + 1);
+    std::vector<uint8_t> nn(M);
+    int64_t pacc = 0, uacc = 0;
+    for (int64_t s = 0; s < M; ++s) {
+      const int fam = b->family ? b->family[s] : b->family_all;
+      const int n = b->n ? b->n[s] : b->n_all;
+      const int alg = b->alg ? b->alg[s] : b->alg_all;
+      poff[s] = b->p_offset ? b->p_offset[s] : pacc;
+      uoff[s] = b->u_offset ? b->u_offset[s] : uacc;
+      pacc = poff[s] + nparams_of(fam, n);
+      uacc = uoff[s] + n;
+      nn[s] = (uint8_t)n;
+      const bool lane = lane_mapped(n);
+      const int key_n = lane ? n : group_bucket(n);
+      const int64_t key = ((int64_t)(lane ? 0 : 1) << 40) | ((int64_t)key_n << 16) | (fam << 8) | alg;
+      buckets[key].push_back((int32_t)s);
+    }
+    poff[M] = pacc;
+    uoff[M] = uacc;
+    std::vector<int32_t> order;
+    order.reserve(M);
+    for (auto& kv : buckets) order.insert(order.end(), kv.second.begin(), kv.second.end());
+    void *dsys = nullptr, *dpo = nullptr, *duo = nullptr, *dn = nullptr;
+    if ((e = db.alloc(&dsys, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&dpo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&duo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&dn, M)) != hipSuccess) return bail(e, "hipMalloc");
+    // these host vectors die with this call: copy synchronously on the stream
+    if ((e = hipMemcpyAsync(dsys, order.data(), M * 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(dpo, poff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(duo, uoff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(dn, nn.data(), M, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+    int64_t at = 0;
+    for (auto& kv : buckets) {
+      const int64_t key = kv.first;
+      const bool lane = ((key >> 40) & 1) == 0;
+      const int key_n = (int)((key >> 16) & 0xff);
+      const int fam = (int)((key >> 8) & 0xff);
+      const int alg = (int)(key & 0xff);
+      KArgs a = base;
+      a.sys = (const int32_t*)dsys + at;
+      a.p_off = (const int64_t*)dpo;
+      a.u_off = (const int64_t*)duo;
+      a.nsys = (const uint8_t*)dn;
+      a.count = (int64_t)kv.second.size();
+      a.P = 0;
+      a.n = key_n;
+      int rcode = launch(key_n, lane, fam, alg, b->precision, a, c->stream);
+      if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
+      if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
+      at += a.count;
+    }
+  }
+
+  if (M > 0 && !dev) {
+    if ((e = hipMemcpyAsync(r->u, d_u, utotal * 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(r->fnorm_inf, d_fn, M * 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(r->iters, d_it, M * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(r->retcode, d_rc, M * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if (r->nfev && (e = hipMemcpyAsync(r->nfev, d_nfev, M * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if (r->njev && (e = hipMemcpyAsync(r->njev, d_njev, M * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+  }
+  if ((e = hipEventRecord(t.stop, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+  if (!dev) {
+    // host payloads: inputs were read from caller memory; make the call
+    // synchronous so that the caller may reuse its buffers at once
+    if ((e = hipEventSynchronize(t.stop)) != hipSuccess) return bail(e, "hipEventSynchronize");
+  }
+  const uint64_t id = c->next_ticket++;
+  t.bytes = held;
+  c->held_bytes += held;
+  c->tickets.emplace(id, std::move(t));
+  *ticket = id;
+  return NLS_OK;
+}
+
+int nls_query(nls_context* c, uint64_t ticket, int32_t wait_ms, nls_ticket_info* info) {
+  if (!c) return fail(nullptr, NLS_E_INVALID, "context is NULL");
+  std::unique_lock<std::mutex> lk(c->mu, std::defer_lock);
+  if (c->flags & NLS_CTX_THREADSAFE) lk.lock();
+  auto it = c->tickets.find(ticket);
+  if (it == c->tickets.end()) return fail(c, NLS_E_NOTFOUND, "unknown ticket");
+  Ticket& t = it->second;
+  hipSetDevice(c->device);
+  hipError_t e = hipEventQuery(t.stop);
+  if (e == hipErrorNotReady) {
+    if (wait_ms == 0) return NLS_PENDING;
+    if (wait_ms < 0) {
+      e = hipEventSynchronize(t.stop);
+    } else {
+      auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(wait_ms);
+      while ((e = hipEventQuery(t.stop)) == hipErrorNotReady) {
+        if (std::chrono::steady_clock::now() >= until) return NLS_PENDING;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+      }
+    }
+  }
+  int32_t status = NLS_OK;
+  float ms = 0.f;
+  if (e != hipSuccess) {
+    status = NLS_E_DEVICE;
+    c->last_error = std::string("ticket failed: ") + hipGetErrorString(e);
+  } else {
+    hipEventElapsedTime(&ms, t.start, t.stop);
+  }
+  if (info) {
+    info->done = 1;
+    info->status = status;
+    info->gpu_ms = ms;
+    info->systems = t.systems;
+  }
+  c->held_bytes -= std::min(c->held_bytes, t.bytes);
+  release_ticket(t, c);
+  c->tickets.erase(it);
+  return status == NLS_OK ? NLS_OK : NLS_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar for the plain FP64 form: identical return codes, iteration counts within
++-1, and ||u_gpu - u_oracle||_inf / ||u_oracle||_inf <= 1e-9 on every system
+both sides solve.  Inputs come from the seeded generators only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_16341_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def nls():
+    from paper_2403_16341_amd import nls as _nls
+    _nls.lib()
+    return _nls
+
+
+@pytest.fixture(scope="module")
+def ctx(nls):
+    c = nls.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(nls, ctx, b, precision=None, opts=None):
+    db = nls.DeviceBatch(b)
+    out = ctx.solve(db, precision=precision, opts=opts)
+    return nls.results_to_numpy(out)
+
+
+def run_oracle(b, opts=None):
+    return oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off,
+                              b.abstol, b.maxiters, opts=opts, nthreads=8)
+
+
+def rel_err(b, ug, uo, s):
+    sl = slice(b.u_off[s], b.u_off[s + 1])
+    den = max(np.abs(uo[sl]).max(), np.finfo(float).tiny)
+    return np.abs(ug[sl] - uo[sl]).max() / den
+
+
+def compare(b, g, o, label, max_rc_mismatch=0, max_u_mismatch=0):
+    """Assert the FP64 parity bar; returns a small report dict."""
+    M = b.M
+    rc_mis = np.nonzero(g["retcode"] != o["retcode"])[0]
+    it_mis = np.nonzero(np.abs(g["iters"].astype(int) - o["iters"]) > 1)[0]
+    both = np.nonzero((g["retcode"] == o["retcode"]) & (o["retcode"] == oracle.RC_SUCCESS))[0]
+    errs = np.array([rel_err(b, g["u"], o["u"], s) for s in both]) if both.size else np.zeros(0)
+    u_mis = both[errs > REL] if errs.size else np.zeros(0, dtype=int)
+    rep = dict(label=label, M=M, rc_mismatch=int(rc_mis.size), iters_mismatch=int(it_mis.size),
+               u_mismatch=int(u_mis.size), max_rel=float(errs.max()) if errs.size else 0.0,
+               success=int((g["retcode"] == 0).sum()))
+    print(rep, flush=True)
+    if rc_mis.size > max_rc_mismatch:
+        s = rc_mis[0]
+        raise AssertionError("%s: %d retcode mismatches, first system %d gpu %d/%d oracle %d/%d"
+                             % (label, rc_mis.size, s, g["retcode"][s], g["iters"][s],
+                                o["retcode"][s], o["iters"][s]))
+    assert u_mis.size <= max_u_mismatch, (label, u_mis[:5], errs.max())
+    # iteration counts: +-1 where the return codes agree
+    agree = g["retcode"] == o["retcode"]
+    assert (np.abs(g["iters"].astype(int) - o["iters"])[agree] <= 1).all(), label
+    # the success invariant holds for every GPU success
+    succ = g["retcode"] == oracle.RC_SUCCESS
+    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+    return rep
+
+
+# ---------------------------------------------------------------------------
+# the workloads at oracle-friendly sizes (several wavefronts plus a ragged tail)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k,M", [(1, 1024), (2, 64 * 9 + 13), (3, 64 * 5 + 21), (4, 1500)])
+def test_workload_parity_fp64(nls, ctx, k, M):
+    b = inputs.config(k, M=M)
+    print("case: workload %d M=%d" % (k, M), flush=True)
+    g = run_gpu(nls, ctx, b)
+    o = run_oracle(b)
+    # the tanh dogleg workload spends up to 100 iterations near non-root
+    # stationary points, where rounding-level differences can flip an
+    # acceptance test; such flips are reported, and must stay rare
+    slack = 0 if k in (1, 2) else max(2, M // 100)
+    compare(b, g, o, "workload%d" % k, max_rc_mismatch=slack, max_u_mismatch=slack)
+
+
+@pytest.mark.parametrize("fam", [inputs.CUBIC, inputs.TANH])
+@pytest.mark.parametrize("alg", [inputs.NEWTON, inputs.ARMIJO, inputs.DOGLEG])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 9, 12, 16, 20, 24, 32, 40, 64])
+def test_family_alg_size_grid(nls, ctx, fam, alg, n):
+    rng = np.random.Generator(np.random.PCG64(1000 + 10 * n + fam))
+    M = 70 if n <= 16 else 23
+    if fam == inputs.CUBIC:
+        p = inputs.cubic_params(rng, M, n)
+        u0 = rng.uniform(-3, 3, (M, n))
+    else:
+        p = inputs.tanh_params(rng, M, n)
+        u0 = rng.uniform(-4, 4, (M, n))
+    b = inputs.homogeneous(fam, n, alg, p, u0, 1e-10, 40)
+    print("case: fam=%d alg=%d n=%d" % (fam, alg, n), flush=True)
+    g = run_gpu(nls, ctx, b)
+    o = run_oracle(b)
+    slack = 0 if fam == inputs.CUBIC and n <= 16 else max(1, M // 20)
+    compare(b, g, o, "fam%d-alg%d-n%d" % (fam, alg, n), max_rc_mismatch=slack, max_u_mismatch=slack)
+
+
+def test_edge_families_and_cases(nls, ctx):
+    cases = [
+        inputs.rosenbrock(100, 10, seed=5, alg=inputs.NEWTON),
+        inputs.rosenbrock(100, 8, seed=6, alg=inputs.DOGLEG),
+        inputs.rosenbrock(7, 10, seed=7, alg=inputs.ARMIJO, u0="paper"),
+        inputs.paper_example(64, seed=8, alg=inputs.NEWTON),
+        inputs.paper_example(64, seed=9, alg=inputs.DOGLEG),
+        inputs.singular_cubic(5, 3),
+        inputs.singular_cubic(5, 12, alg=inputs.DOGLEG),
+        inputs.no_root_tanh(20, 5, seed=10),
+        inputs.no_root_tanh(20, 11, seed=11, alg=inputs.DOGLEG),
+        inputs.separable_cubic(30, 4, seed=12),
+        inputs.separable_tanh(30, 6, seed=13),
+    ]
+    for b in cases:
+        print("case:", b.name, b.M, int(b.n[0]), int(b.alg[0]), flush=True)
+        compare(b, run_gpu(nls, ctx, b), run_oracle(b), b.name)
+
+
+def test_nonfinite_maxiters_and_empty(nls, ctx):
+    b = inputs.config(2, M=130)
+    b.u0[8 * 3 + 2] = np.nan          # system 3 starts at NaN
+    b.params[72 * 5 + 10] = np.inf    # system 5 has an infinite parameter
+    g = run_gpu(nls, ctx, b)
+    o = run_oracle(b)
+    compare(b, g, o, "nonfinite")
+    assert g["retcode"][3] == oracle.RC_NONFINITE and g["iters"][3] == 0
+    assert g["retcode"][5] == oracle.RC_NONFINITE
+    b0 = inputs.config(1, M=100)
+    b0.maxiters = 0
+    g = run_gpu(nls, ctx, b0)
+    assert (g["retcode"] == oracle.RC_MAXITERS).all() and (g["iters"] == 0).all()
+    e = inputs.config(1, M=0)
+    g = run_gpu(nls, ctx, e)
+    assert g["retcode"].size == 0
+
+
+def test_host_and_device_paths_agree_and_repeat_bitwise(nls, ctx):
+    b = inputs.config(4, M=900)
+    g1 = run_gpu(nls, ctx, b)
+    g2 = run_gpu(nls, ctx, b)
+    h = nls.solve_host(ctx, b)
+    for key in ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev"):
+        assert np.array_equal(g1[key], g2[key], equal_nan=True), key
+        assert np.array_equal(g1[key], h[key], equal_nan=True), key
+
+
+def test_ragged_offsets_with_gaps(nls, ctx):
+    """Systems placed at offsets with gaps between them (spans longer than the
+    parameter and unknown counts), solved through both payload kinds."""
+    b = inputs.config(4, M=300)
+    p_off = b.p_off + 3 * np.arange(b.M + 1, dtype=np.int64)
+    u_off = b.u_off + 2 * np.arange(b.M + 1, dtype=np.int64)
+    params = np.full(p_off[-1], np.nan)
+    u0 = np.full(u_off[-1], 7.0)
+    for s in range(b.M):
+        P = b.p_off[s + 1] - b.p_off[s]
+        params[p_off[s]:p_off[s] + P] = b.params[b.p_off[s]:b.p_off[s + 1]]
+        u0[u_off[s]:u_off[s] + b.n[s]] = b.u0[b.u_off[s]:b.u_off[s + 1]]
+    gb = inputs.Batch(b.family, b.n, b.alg, params, p_off, u0, u_off, b.abstol, b.maxiters)
+    h = nls.solve_host(ctx, gb)
+    d = run_gpu(nls, ctx, gb)
+    ref = run_gpu(nls, ctx, b)
+    for s in range(b.M):
+        a = h["u"][u_off[s]:u_off[s] + b.n[s]]
+        assert np.array_equal(a, ref["u"][b.u_off[s]:b.u_off[s + 1]])
+        assert np.array_equal(a, d["u"][u_off[s]:u_off[s] + b.n[s]])
+    gaps = np.ones(u_off[-1], bool)
+    for s in range(b.M):
+        gaps[u_off[s]:u_off[s] + b.n[s]] = False
+    assert (h["u"][gaps] == 7.0).all()
+    for key in ("iters", "retcode", "fnorm_inf", "nfev", "njev"):
+        assert np.array_equal(h[key], ref[key]) and np.array_equal(d[key], ref[key])
+
+
+def test_fp32_inner_classification(nls, ctx):
+    """FP32-inner against the FP64 oracle: every GPU success meets the test, the
+    unique-root cubic workloads reach the oracle's root, and tanh systems are
+    classified same root / other root / failure."""
+    for k, M in ((1, 1024), (2, 700), (3, 400)):
+        b = inputs.config(k, M=M)
+        g = run_gpu(nls, ctx, b, precision=inputs.PREC_FP32_INNER)
+        o = run_oracle(b)
+        succ = g["retcode"] == oracle.RC_SUCCESS
+        assert (g["fnorm_inf"][succ] <= b.abstol).all()
+        if k in (1, 2):
+            assert succ.all()
+            errs = np.array([rel_err(b, g["u"], o["u"], s) for s in range(M)])
+            # a root of a strongly monotone map: error <= ||J^-1|| abstol, ~1e-10
+            assert errs.max() <= 1e-8, errs.max()
+        else:
+            both = succ & (o["retcode"] == oracle.RC_SUCCESS)
+            errs = np.array([rel_err(b, g["u"], o["u"], s) for s in np.nonzero(both)[0]])
+            same = (errs <= 1e-8).sum()
+            print("fp32-inner workload3: gpu success %d, oracle success %d, same root %d of %d"
+                  % (succ.sum(), (o["retcode"] == 0).sum(), same, both.sum()), flush=True)
+            assert same >= 0.9 * both.sum()
+
+
+def test_full_size_headline_sampled(nls, ctx):
+    """The 2^20 x N=8 Armijo workload in the launch the benchmark times: sampled
+    systems against the oracle one by one, plus properties on every system."""
+    b = inputs.config(2)
+    g = run_gpu(nls, ctx, b)
+    assert (g["retcode"] == oracle.RC_SUCCESS).all()
+    assert (g["fnorm_inf"] <= b.abstol).all()
+    assert g["iters"].min() >= 1 and g["iters"].max() <= 10
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.sort(rng.choice(b.M, 3000, replace=False))
+    sub = b.subset(idx)
+    o = run_oracle(sub)
+    gs = {k: (v[idx] if k != "u" else np.concatenate([v[b.u_off[s]:b.u_off[s + 1]] for s in idx]))
+          for k, v in g.items()}
+    compare(sub, gs, o, "headline-sampled")
