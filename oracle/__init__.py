@@ -37,17 +37,29 @@ TRACE_FIELDS = [
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
-def build(force: bool = False) -> str:
-    """Compile ``liboracle.so`` with gcc (no contraction, no fast-math)."""
-    if (not force and os.path.exists(_LIB)
-            and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)
-            and os.path.getmtime(_LIB) >= os.path.getmtime(os.path.join(_HERE, "nls_oracle.h"))):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm", "-lpthread"]
+# Build variants.  "plain" is the oracle.  "fma" is the same source compiled
+# with multiply-add contraction: a rounding-level perturbation of the same
+# arithmetic, used only to tell which systems are sensitive to rounding.
+VARIANTS = {
+    "plain": ("liboracle.so", []),
+    "fma": ("liboracle_fma.so", ["-mfma", "-ffp-contract=fast"]),
+}
+
+
+def build(force: bool = False, variant: str = "plain") -> str:
+    """Compile the oracle library with gcc (plain: no contraction, no fast-math)."""
+    name, extra = VARIANTS[variant]
+    out = os.path.join(_HERE, name)
+    if (not force and os.path.exists(out)
+            and os.path.getmtime(out) >= os.path.getmtime(_SRC)
+            and os.path.getmtime(out) >= os.path.getmtime(os.path.join(_HERE, "nls_oracle.h"))):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    flags = [f for f in CFLAGS if not (extra and f == "-ffp-contract=off")]
+    cmd = ["gcc", *flags, *extra, "-o", tmp, _SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, out)
+    return out
 
 
 class _Opts(ctypes.Structure):
@@ -75,13 +87,16 @@ class _Result(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = ctypes.CDLL(build())
+def lib(variant: str = "plain"):
+    if variant not in _libs:
+        # NLS_ORACLE_LIB points the pins at another build of the oracle (the
+        # mutation test plants mistakes in a copy and checks the pins fail)
+        path = os.environ.get("NLS_ORACLE_LIB") if variant == "plain" else None
+        _lib = ctypes.CDLL(path or build(variant=variant))
+        _libs[variant] = _lib
         P = ctypes.c_void_p
         _lib.or_default_opts.argtypes = [ctypes.POINTER(_Opts)]
         _lib.or_nparams.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -98,7 +113,7 @@ def lib():
         _lib.or_solve_batch.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                         ctypes.c_int32, ctypes.POINTER(_Opts), P, P, P, P, P, P,
                                         ctypes.c_int32]
-    return _lib
+    return _libs[variant]
 
 
 def _ptr(a):
@@ -184,7 +199,7 @@ def solve_one(family: int, alg: int, p, u0, abstol: float = 1e-10, maxiters: int
 
 
 def solve_batch(family, n, alg, params, p_off, u0, u_off, abstol: float, maxiters: int,
-                opts: dict | None = None, nthreads: int = 1) -> dict:
+                opts: dict | None = None, nthreads: int = 1, variant: str = "plain") -> dict:
     """Batch solve.  family/n/alg: uint8[M]; p_off/u_off: int64[M+1] prefix offsets."""
     family = np.ascontiguousarray(family, dtype=np.uint8)
     n = np.ascontiguousarray(n, dtype=np.uint8)
@@ -201,7 +216,7 @@ def solve_batch(family, n, alg, params, p_off, u0, u_off, abstol: float, maxiter
     nfev = np.empty(M, dtype=np.int32)
     njev = np.empty(M, dtype=np.int32)
     o = _make_opts(opts)
-    lib().or_solve_batch(M, _ptr(family), _ptr(n), _ptr(alg), _ptr(params), _ptr(p_off),
+    lib(variant).or_solve_batch(M, _ptr(family), _ptr(n), _ptr(alg), _ptr(params), _ptr(p_off),
                          _ptr(u0), _ptr(u_off), float(abstol), int(maxiters), ctypes.byref(o),
                          _ptr(u), _ptr(fnorm), _ptr(iters), _ptr(rc), _ptr(nfev), _ptr(njev),
                          int(nthreads))

@@ -340,6 +340,10 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       if (b->p_offset) ptotal = std::max(ptotal, pe); else ptotal = pe;
       if (b->u_offset) utotal = std::max(utotal, ue); else utotal = ue;
     }
+    // the extents run to the final offsets, so gaps inside the last span are
+    // staged (and, for u, returned) like every other gap
+    if (b->p_offset) ptotal = std::max(ptotal, b->p_offset[M]);
+    if (b->u_offset) utotal = std::max(utotal, b->u_offset[M]);
   }
 
   // device footprint of this call (library-owned memory only)

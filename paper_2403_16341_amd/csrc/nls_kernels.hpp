@@ -233,7 +233,6 @@ template <int N> struct LaneFam<N, FAM_PAPER> {
 template <int N, typename T>
 __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
   bool ok = true;
-  T rdiag[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     // first maximum of |a_ik|, i >= k, in current row order
@@ -246,24 +245,27 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
       best = c ? v : best;
       p = c ? i : p;
     }
-    // exchange rows k and p (columns k.. and the RHS) with selects
+    // exchange rows k and p (columns k.. and the RHS) with selects; the whole
+    // network is skipped when no lane of the wavefront needs an exchange
+    if (__any(p != k)) {
 #pragma unroll
-    for (int i = k + 1; i < N; ++i) {
-      const bool sel = (p == i);
+      for (int i = k + 1; i < N; ++i) {
+        const bool sel = (p == i);
 #pragma unroll
-      for (int j = k; j < N; ++j) {
-        T t = a[k][j];
-        a[k][j] = sel ? a[i][j] : t;
-        a[i][j] = sel ? t : a[i][j];
+        for (int j = k; j < N; ++j) {
+          T t = a[k][j];
+          a[k][j] = sel ? a[i][j] : t;
+          a[i][j] = sel ? t : a[i][j];
+        }
+        T t = x[k];
+        x[k] = sel ? x[i] : t;
+        x[i] = sel ? t : x[i];
       }
-      T t = x[k];
-      x[k] = sel ? x[i] : t;
-      x[i] = sel ? t : x[i];
     }
     const T piv = a[k][k];
     ok = ok && (piv != T(0)) && fin(piv);
     const T r = T(1) / piv;
-    rdiag[k] = r;
+    a[k][k] = r;  // the pivot is only needed as its reciprocal from here on
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
       const T l = a[i][k] * r;
@@ -277,7 +279,7 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
     T s = x[i];
 #pragma unroll
     for (int j = i + 1; j < N; ++j) s = __builtin_fma(-a[i][j], x[j], s);
-    x[i] = s * rdiag[i];
+    x[i] = s * a[i][i];
   }
   return ok;
 }
@@ -664,7 +666,7 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
   const bool own = r < n;
   int pos = own ? r : NB + 1 + r;  // logical row position; non-rows never pivot
   bool ok = true;
-  TI rdiag[NB];
+  TI myrd = TI(0);  // reciprocal of this row's pivot, once it has been the pivot row
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     if (k < n) {
@@ -693,8 +695,8 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
       const TI pv = sh.piv[gi][k];
       ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
       const TI rp = TI(1) / pv;
-      rdiag[k] = rp;
       // exchange of logical positions k <-> kp
+      if (pos == kp) myrd = rp;
       if (pos == kp) pos = k;
       else if (pos == k) pos = kp;
       if (own && pos > k) {
@@ -711,7 +713,7 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
 #pragma unroll
   for (int k = NB - 1; k >= 0; --k) {
     if (k < n) {
-      if (pos == k) sh.sol[gi][k] = rhs * rdiag[k];
+      if (pos == k) sh.sol[gi][k] = rhs * myrd;
       wave_sync();
       if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
       wave_sync();

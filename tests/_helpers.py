@@ -1,0 +1,103 @@
+"""Shared test helpers: an independent numpy residual and the parity
+classification of GPU results against the oracle."""
+import numpy as np
+
+import oracle
+
+REL = 1e-9
+STALLS = (oracle.RC_MAXITERS, oracle.RC_LINESEARCH_FAILED, oracle.RC_TR_COLLAPSED)
+
+
+def np_residual(family, p, u):
+    """Residual families written out in numpy (independent of both sides)."""
+    n = u.size
+    if family == oracle.CUBIC:
+        return p[: n * n].reshape(n, n) @ u + 0.1 * u ** 3 - p[n * n: n * n + n]
+    if family == oracle.TANH:
+        return p[: n * n].reshape(n, n) @ np.tanh(u) + p[n * n + n] * u - p[n * n: n * n + n]
+    if family == oracle.ROSENBROCK:
+        return np.concatenate([[1 - u[0]], 10 * (u[1:] - u[:-1] ** 2)])
+    a, b_, c = p
+    return np.array([(u[0] + a) * (u[1] ** 3 - b_) + c, np.sin(u[1] * np.exp(u[0]) - 1)])
+
+
+def run_oracle(b, opts=None, variant="plain", u0=None):
+    return oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0 if u0 is None else u0,
+                              b.u_off, b.abstol, b.maxiters, opts=opts, nthreads=8, variant=variant)
+
+
+def rel_err(b, ug, uo, s):
+    sl = slice(b.u_off[s], b.u_off[s] + b.n[s])
+    den = max(np.abs(uo[sl]).max(), np.finfo(float).tiny)
+    return np.abs(ug[sl] - uo[sl]).max() / den
+
+
+def _same(b, x, y, s):
+    """Two oracle runs agree on system s: same return code, iterations within
+    +-1, and final iterates that did not separate (1e-9 relative for a
+    success; 1e-6 for a failure, whose end point tracks the trajectory)."""
+    if x["retcode"][s] != y["retcode"][s] or abs(int(x["iters"][s]) - int(y["iters"][s])) > 1:
+        return False
+    e = rel_err(b, x["u"], y["u"], s)
+    if not np.isfinite(e):
+        return x["retcode"][s] == y["retcode"][s] == oracle.RC_NONFINITE
+    return e <= (REL if x["retcode"][s] == oracle.RC_SUCCESS else 1e-6)
+
+
+def classify(b, g, opts=None, strict_all=False):
+    """Compare GPU results g with the oracle.
+
+    A system is rounding-sensitive when the oracle's own outcome changes under
+    a rounding-level perturbation: the same source built with multiply-add
+    contraction, u0 moved by one ulp either way, or both.  Every other system must meet the
+    strict bar (identical return code, iterations within +-1, relative u error
+    <= 1e-9), except that two runs stalled at the same non-root point (u within
+    1e-6) count as one outcome whichever stop test ended them.  Sensitive systems must still satisfy the invariants, and where
+    both sides succeed, agree within the forward-error bound of the stopping
+    test, 2 ||J(u*)^-1||_inf abstol (or have reached another valid root)."""
+    o = run_oracle(b, opts)
+    up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
+    probes = [run_oracle(b, opts, variant="fma"), run_oracle(b, opts, u0=up), run_oracle(b, opts, u0=dn),
+              run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn)]
+    M = b.M
+    sens = np.array([not all(_same(b, o, q, s) for q in probes) for s in range(M)], dtype=bool)
+    if strict_all:
+        sens[:] = False
+    report = dict(M=M, sensitive=int(sens.sum()), success_gpu=int((g["retcode"] == 0).sum()),
+                  success_oracle=int((o["retcode"] == 0).sum()), strict_fail=[], sens_rc_diff=0,
+                  other_root=0, same_stall=0, max_rel_strict=0.0)
+    for s in range(M):
+        gs, os_ = int(g["retcode"][s]), int(o["retcode"][s])
+        f_, n, _, p, _ = b.system(s)
+        if gs == oracle.RC_SUCCESS:
+            ug = g["u"][b.u_off[s]:b.u_off[s] + n]
+            assert g["fnorm_inf"][s] <= b.abstol, (s, g["fnorm_inf"][s])
+            Fn = np.abs(np_residual(f_, p, ug)).max()
+            assert Fn <= b.abstol * (1 + 1e-6) + 1e-13, (s, Fn)
+        if not sens[s]:
+            ok = gs == os_ and abs(int(g["iters"][s]) - int(o["iters"][s])) <= 1
+            if ok and gs == oracle.RC_SUCCESS:
+                e = rel_err(b, g["u"], o["u"], s)
+                report["max_rel_strict"] = max(report["max_rel_strict"], e)
+                ok = e <= REL
+            if not ok and gs in STALLS and os_ in STALLS and rel_err(b, g["u"], o["u"], s) <= 1e-6:
+                # both stalled at the same non-root point; which stop test fires
+                # first (radius collapse, failed search or the cap) is set by rounding
+                report["same_stall"] += 1
+                ok = True
+            if not ok:
+                report["strict_fail"].append((s, gs, int(g["iters"][s]), os_, int(o["iters"][s])))
+        else:
+            if gs != os_:
+                report["sens_rc_diff"] += 1
+            if gs == os_ == oracle.RC_SUCCESS:
+                uo = o["u"][b.u_off[s]:b.u_off[s] + n]
+                J = oracle.jacobian(f_, p, uo)
+                try:
+                    kappa = np.abs(np.linalg.inv(J)).sum(axis=1).max()
+                except np.linalg.LinAlgError:
+                    kappa = np.inf
+                bound = 2 * kappa * b.abstol / max(np.abs(uo).max(), 1e-300) + REL
+                if rel_err(b, g["u"], o["u"], s) > bound:
+                    report["other_root"] += 1
+    return report, o

@@ -12,7 +12,7 @@ from paper_2403_16341_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-REL = 1e-9
+from _helpers import REL, classify, rel_err, run_oracle
 
 
 @pytest.fixture(scope="module")
@@ -35,41 +35,13 @@ def run_gpu(nls, ctx, b, precision=None, opts=None):
     return nls.results_to_numpy(out)
 
 
-def run_oracle(b, opts=None):
-    return oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off,
-                              b.abstol, b.maxiters, opts=opts, nthreads=8)
-
-
-def rel_err(b, ug, uo, s):
-    sl = slice(b.u_off[s], b.u_off[s + 1])
-    den = max(np.abs(uo[sl]).max(), np.finfo(float).tiny)
-    return np.abs(ug[sl] - uo[sl]).max() / den
-
-
-def compare(b, g, o, label, max_rc_mismatch=0, max_u_mismatch=0):
-    """Assert the FP64 parity bar; returns a small report dict."""
-    M = b.M
-    rc_mis = np.nonzero(g["retcode"] != o["retcode"])[0]
-    it_mis = np.nonzero(np.abs(g["iters"].astype(int) - o["iters"]) > 1)[0]
-    both = np.nonzero((g["retcode"] == o["retcode"]) & (o["retcode"] == oracle.RC_SUCCESS))[0]
-    errs = np.array([rel_err(b, g["u"], o["u"], s) for s in both]) if both.size else np.zeros(0)
-    u_mis = both[errs > REL] if errs.size else np.zeros(0, dtype=int)
-    rep = dict(label=label, M=M, rc_mismatch=int(rc_mis.size), iters_mismatch=int(it_mis.size),
-               u_mismatch=int(u_mis.size), max_rel=float(errs.max()) if errs.size else 0.0,
-               success=int((g["retcode"] == 0).sum()))
-    print(rep, flush=True)
-    if rc_mis.size > max_rc_mismatch:
-        s = rc_mis[0]
-        raise AssertionError("%s: %d retcode mismatches, first system %d gpu %d/%d oracle %d/%d"
-                             % (label, rc_mis.size, s, g["retcode"][s], g["iters"][s],
-                                o["retcode"][s], o["iters"][s]))
-    assert u_mis.size <= max_u_mismatch, (label, u_mis[:5], errs.max())
-    # iteration counts: +-1 where the return codes agree
-    agree = g["retcode"] == o["retcode"]
-    assert (np.abs(g["iters"].astype(int) - o["iters"])[agree] <= 1).all(), label
-    # the success invariant holds for every GPU success
-    succ = g["retcode"] == oracle.RC_SUCCESS
-    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+def compare(b, g, label, opts=None, max_other_root=0, strict_all=False):
+    """Parity bar on one batch (see _helpers.classify); returns the report."""
+    rep, o = classify(b, g, opts=opts, strict_all=strict_all)
+    rep["label"] = label
+    print({k: (v[:5] if isinstance(v, list) else v) for k, v in rep.items()}, flush=True)
+    assert not rep["strict_fail"], (label, rep["strict_fail"][:5])
+    assert rep["other_root"] <= max_other_root, (label, rep["other_root"])
     return rep
 
 
@@ -81,12 +53,9 @@ def test_workload_parity_fp64(nls, ctx, k, M):
     b = inputs.config(k, M=M)
     print("case: workload %d M=%d" % (k, M), flush=True)
     g = run_gpu(nls, ctx, b)
-    o = run_oracle(b)
-    # the tanh dogleg workload spends up to 100 iterations near non-root
-    # stationary points, where rounding-level differences can flip an
-    # acceptance test; such flips are reported, and must stay rare
-    slack = 0 if k in (1, 2) else max(2, M // 100)
-    compare(b, g, o, "workload%d" % k, max_rc_mismatch=slack, max_u_mismatch=slack)
+    rep = compare(b, g, "workload%d" % k, max_other_root=0 if k < 3 else M // 50)
+    if k in (1, 2):
+        assert rep["sensitive"] == 0
 
 
 @pytest.mark.parametrize("fam", [inputs.CUBIC, inputs.TANH])
@@ -104,9 +73,7 @@ def test_family_alg_size_grid(nls, ctx, fam, alg, n):
     b = inputs.homogeneous(fam, n, alg, p, u0, 1e-10, 40)
     print("case: fam=%d alg=%d n=%d" % (fam, alg, n), flush=True)
     g = run_gpu(nls, ctx, b)
-    o = run_oracle(b)
-    slack = 0 if fam == inputs.CUBIC and n <= 16 else max(1, M // 20)
-    compare(b, g, o, "fam%d-alg%d-n%d" % (fam, alg, n), max_rc_mismatch=slack, max_u_mismatch=slack)
+    compare(b, g, "fam%d-alg%d-n%d" % (fam, alg, n), max_other_root=M // 10 if fam == inputs.TANH else 0)
 
 
 def test_edge_families_and_cases(nls, ctx):
@@ -125,7 +92,7 @@ def test_edge_families_and_cases(nls, ctx):
     ]
     for b in cases:
         print("case:", b.name, b.M, int(b.n[0]), int(b.alg[0]), flush=True)
-        compare(b, run_gpu(nls, ctx, b), run_oracle(b), b.name)
+        compare(b, run_gpu(nls, ctx, b), b.name)
 
 
 def test_nonfinite_maxiters_and_empty(nls, ctx):
@@ -133,8 +100,7 @@ def test_nonfinite_maxiters_and_empty(nls, ctx):
     b.u0[8 * 3 + 2] = np.nan          # system 3 starts at NaN
     b.params[72 * 5 + 10] = np.inf    # system 5 has an infinite parameter
     g = run_gpu(nls, ctx, b)
-    o = run_oracle(b)
-    compare(b, g, o, "nonfinite")
+    compare(b, g, "nonfinite")
     assert g["retcode"][3] == oracle.RC_NONFINITE and g["iters"][3] == 0
     assert g["retcode"][5] == oracle.RC_NONFINITE
     b0 = inputs.config(1, M=100)
@@ -219,7 +185,7 @@ def test_full_size_headline_sampled(nls, ctx):
     rng = np.random.Generator(np.random.PCG64(77))
     idx = np.sort(rng.choice(b.M, 3000, replace=False))
     sub = b.subset(idx)
-    o = run_oracle(sub)
     gs = {k: (v[idx] if k != "u" else np.concatenate([v[b.u_off[s]:b.u_off[s + 1]] for s in idx]))
-          for k, v in g.items()}
-    compare(sub, gs, o, "headline-sampled")
+          for k, v in g.items() if isinstance(v, np.ndarray)}
+    rep = compare(sub, gs, "headline-sampled")
+    assert rep["sensitive"] == 0

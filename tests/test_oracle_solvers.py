@@ -266,6 +266,9 @@ def test_dogleg_invariants(k):
                 gn, tc = t["gnorm"][i], t["cauchy"][i]
                 slack = 64 * np.finfo(float).eps * t["merit_before"][i]   # cancellation in pred
                 assert t["pred"][i] >= gn * min(D, tc * gn) * (1 - 1e-9) - slack
+            if kind != 0:
+                # the Newton step does not fit: the dogleg step ends on the sphere
+                assert abs(step - D) <= 1e-12 * D
             if t["accepted"][i] == 1:
                 assert t["merit"][i] < t["merit_before"][i]
                 if merit_prev is not None:
@@ -431,3 +434,39 @@ def test_tanh_success_is_within_kantorovich_radius_of_a_true_root():
         L = mpmath.mpf("0.7699") * max(mpmath.fsum(abs(A[i, j]) for j in range(n)) for i in range(n))
         assert b0 * eta * L <= 0.5
         assert 2 * eta <= 1e-8 * max(1.0, float(mpmath.mnorm(mpmath.matrix(u.tolist()), "inf")))
+
+
+def _armijo_edge_start(ratio_target):
+    """1-D tanh system a tanh(u) + beta u - b with a start u0 whose full Newton
+    step changes the merit by the factor ratio_target (found by bisection on
+    u0 with an independent numpy Newton step)."""
+    a, beta, bb = 2.0, 0.1, 0.5
+
+    def ratio(u):
+        F = a * np.tanh(u) + beta * u - bb
+        dF = a * (1 - np.tanh(u) ** 2) + beta
+        u1 = u - F / dF
+        F1 = a * np.tanh(u1) + beta * u1 - bb
+        return (F1 / F) ** 2
+
+    lo, hi = 0.8, 3.0        # ratio(lo) < target < ratio(hi)
+    assert ratio(lo) < ratio_target < ratio(hi)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if ratio(mid) < ratio_target:
+            lo = mid
+        else:
+            hi = mid
+    return np.array([a, bb, beta]), np.array([0.5 * (lo + hi)])
+
+
+def test_armijo_sufficient_decrease_constant_at_the_edge():
+    """Sec. 2.2.1 with c = 1e-4: the full step passes only if the merit falls by
+    at least the factor 1 - 2c.  A start whose full step gives the factor
+    0.9999 must backtrack; one giving 0.9997 must accept alpha = 1."""
+    p, u0 = _armijo_edge_start(0.9999)
+    r = oracle.solve_one(oracle.TANH, oracle.ARMIJO, p, u0, abstol=1e-12, maxiters=1, trace_cap=4)
+    assert r["trace"]["alpha"][0] < 1.0
+    p, u0 = _armijo_edge_start(0.9997)
+    r = oracle.solve_one(oracle.TANH, oracle.ARMIJO, p, u0, abstol=1e-12, maxiters=1, trace_cap=4)
+    assert r["trace"]["alpha"][0] == 1.0
