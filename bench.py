@@ -37,6 +37,30 @@ def flops_armijo_cubic(n, iters, nfev):
     return R + iters * (J + LU + TRSV) + trials * (R + 4 * n)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "lane_cubic_n8_armijo_fp64_1M.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("nls_kernels.hpp", "nls_lane_dispatch.inc", "nls_types.h"):
+        h.update(open(os.path.join(ROOT, "paper_2403_16341_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed rocprofv3 summary, if it was
+    taken on the kernel as it is now (same source hash); else None."""
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in txt.splitlines() if l.startswith(("traffic_bytes_per_launch", "source_hash")))
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def run_form(nls, ctx, db, precision, steps, warmup, with_counters=False):
     import torch
     out = db.alloc_results()
@@ -65,6 +89,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--systems", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,fp32", help="precision forms to time (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
@@ -74,6 +101,17 @@ def main():
     import torch
     from paper_2403_16341_amd import inputs, nls
 
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes MIB MiB each launch
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 10}))
+        return
+
     b = inputs.config(2, M=args.systems)
     M, n = b.M, 8
     print("[bench] workload %s: %d systems, generated" % (b.name, M), file=sys.stderr, flush=True)
@@ -81,6 +119,18 @@ def main():
     db = nls.DeviceBatch(b)
     torch.cuda.synchronize()
 
+    forms = args.forms.split(",")
+    if forms == ["fp64"]:
+        # profiling run: time the plain form only and stop
+        out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
+        print("[bench] fp64: %.3f ms/step, kernel %.3f ms" % (step64 * 1e3, np.mean(gpu64)), file=sys.stderr)
+        ctx.close()
+        return
+    if forms == ["fp32"]:
+        out32, step32, gpu32 = run_form(nls, ctx, db, inputs.PREC_FP32_INNER, args.steps, args.warmup)
+        print("[bench] fp32-inner: %.3f ms/step, kernel %.3f ms" % (step32 * 1e3, np.mean(gpu32)), file=sys.stderr)
+        ctx.close()
+        return
     out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
     rc64 = out64["retcode"].cpu().numpy()
     conv64 = int((rc64 == 0).sum())
@@ -122,7 +172,7 @@ def main():
                                "u0~U(-3,3), abstol 1e-10, maxiters 100",
                    "systems": M, "n": n, "family": "cubic", "alg": "newton_armijo", "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                      "kernel": "k_lane<8,cubic,armijo,double>", "kernel_ms": kernel_ms,
                      "bytes_per_system": bytes_per_system},
         "flop_model": {"flops": flops, "tflops": flops / (kernel_ms * 1e-3) / 1e12,

@@ -92,6 +92,7 @@ template <int N, int FAM> struct LaneFam;
 template <int N> struct LaneFam<N, FAM_CUBIC> {
   double A[N][N];
   double b[N];
+  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -127,6 +128,7 @@ template <int N> struct LaneFam<N, FAM_TANH> {
   double A[N][N];
   double b[N];
   double beta;
+  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -165,6 +167,7 @@ template <int N> struct LaneFam<N, FAM_TANH> {
 };
 
 template <int N> struct LaneFam<N, FAM_ROSENBROCK> {
+  __device__ __forceinline__ void load_lds(const double*) {}
   __device__ __forceinline__ void load(const double* __restrict__) {}
   __device__ __forceinline__ void residual(const double (&u)[N], double (&F)[N], double (&aux)[N]) const {
     F[0] = 1.0 - u[0];
@@ -197,6 +200,7 @@ template <int N> struct LaneFam<N, FAM_ROSENBROCK> {
 template <int N> struct LaneFam<N, FAM_PAPER> {
   static_assert(N == 2, "the workflow example has two unknowns");
   double a, b, c;
+  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
     a = p[0];
     b = p[1];
@@ -304,210 +308,311 @@ template <int N, typename T> __device__ __forceinline__ T sumsq(const T (&x)[N])
 }
 
 // ---------------------------------------------------------------------------
-// Lane-mapping solver kernel: one system per lane.
+// Lane-mapping solver kernel: one system per lane, persistent wavefronts.
+//
+// Each wavefront walks the 64-system chunks blockIdx.x, blockIdx.x +
+// gridDim.x, ...  A lane whose system finishes writes its results and takes
+// the next system of the wavefront's current chunk (retire and refill), so a
+// wavefront does not wait for its slowest lane.  Every trip of the main loop
+// runs one phase-uniform step: a factorisation for the lanes that need a new
+// direction, then one residual evaluation for every lane holding a trial
+// point.  When the batch is uniform and packed, the parameters of the next
+// chunk are copied into LDS with coalesced global->LDS loads as soon as the
+// previous chunk has been handed out, so the copy overlaps the solve.
 // ---------------------------------------------------------------------------
+template <int N, int FAM> struct LaneParams {
+  static constexpr int P = FAM == FAM_CUBIC ? N * N + N
+                         : FAM == FAM_TANH ? N * N + N + 1
+                         : FAM == FAM_PAPER ? 3 : 0;
+};
+
+enum : int { ST_IDLE = 0, ST_DIR = 1, ST_TRIAL = 2 };
+
+// copy `bytes` (a multiple of 8) from global memory into LDS, 16 bytes per
+// lane per instruction and a 4-byte-granule tail; asynchronous until the next
+// s_waitcnt
+__device__ __forceinline__ void stage_to_lds(const double* __restrict__ src, double* dst, int64_t bytes) {
+  const int lane = threadIdx.x;
+  const char* g = reinterpret_cast<const char*>(src);
+  char* l = reinterpret_cast<char*>(dst);
+  const int64_t full = bytes & ~int64_t(1023);
+  for (int64_t off = 0; off < full; off += 1024) {
+    __builtin_amdgcn_global_load_lds(g + off + lane * 16,
+                                     (__attribute__((address_space(3))) void*)(l + off), 16, 0, 0);
+  }
+  // remainder (a multiple of 8 bytes): 4 bytes per lane per instruction
+  for (int64_t off = full; off < bytes; off += 256) {
+    if (off + lane * 4 < bytes)
+      __builtin_amdgcn_global_load_lds(g + off + lane * 4,
+                                       (__attribute__((address_space(3))) void*)(l + off), 4, 0, 0);
+  }
+}
+
 template <int N, int FAM, int ALG, typename TI>
 __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (t >= a.count) return;
-  const int64_t s = a.sys ? (int64_t)a.sys[t] : t;
-  const double* __restrict__ p = a.params + (a.p_off ? a.p_off[s] : s * a.P);
-  const int64_t uo = a.u_off ? a.u_off[s] : s * N;
+  constexpr int P = LaneParams<N, FAM>::P;
+  constexpr int PS = P > 0 ? P : 1;
+  __shared__ __attribute__((aligned(16))) double stage[64 * PS];
 
-  LaneFam<N, FAM> fam;
-  fam.load(p);
-  double u[N], F[N], aux[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) u[i] = a.u0[uo + i];
-  fam.residual(u, F, aux);
-
-  int32_t rc = RC_MAXITERS, it = 0, nf = 1, nj = 0;
+  const int lane = threadIdx.x;
+  const bool staged = P > 0 && a.sys == nullptr && a.p_off == nullptr;
+  const int64_t nchunks = (a.count + 63) / 64;
   const double tol = a.abstol;
   const int32_t maxit = a.maxiters;
-  bool done = true;
-  if (!all_finite(F)) {
-    rc = RC_NONFINITE;
-  } else if (norm_inf(F) <= tol) {
-    rc = RC_SUCCESS;
-  } else {
-    done = false;
-  }
+  const double c2 = 2.0 * a.o.armijo_c;
+  const double rho_bt = a.o.armijo_rho;
+  const int32_t mh = a.o.armijo_max_halvings;
+  const DoglegOpts o = a.o.dogleg();
 
-  if (!done && ALG == ALG_NEWTON) {
-    // J_k delta = -F(u_k); u_{k+1} = u_k + delta
-    int k = 1;
-    for (; k <= maxit; ++k) {
-      TI J[N][N], x[N];
-      fam.template jacobian<TI>(u, aux, J);
-#pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = (TI)(-F[i]);
-      ++nj;
-      if (!lane_lu_solve<N, TI>(J, x)) { rc = RC_SINGULAR; break; }
-#pragma unroll
-      for (int i = 0; i < N; ++i) u[i] += (double)x[i];
-      fam.residual(u, F, aux);
-      ++nf;
-      if (!all_finite(F)) { rc = RC_NONFINITE; break; }
-      if (norm_inf(F) <= tol) { rc = RC_SUCCESS; break; }
+  // chunk currently being handed out (wave-uniform)
+  int64_t chunk = blockIdx.x;
+  int buf_next = 0, buf_cnt = 0;
+  bool buf_wait = false;
+  if (chunk < nchunks) {
+    buf_cnt = (int)min<int64_t>(64, a.count - chunk * 64);
+    if (staged) {
+      stage_to_lds(a.params + chunk * 64 * (int64_t)P, stage, (int64_t)buf_cnt * P * 8);
+      buf_wait = true;
     }
-    it = k > maxit ? maxit : k;
   }
 
-  if (!done && ALG == ALG_ARMIJO) {
-    // backtracking on alpha = rho^m until ||F(u + alpha d)||^2 <= (1 - 2 c alpha) ||F(u)||^2
-    const double c2 = 2.0 * a.o.armijo_c;
-    const double rho = a.o.armijo_rho;
-    const int32_t mh = a.o.armijo_max_halvings;
-    int k = 1;
-    for (; k <= maxit; ++k) {
-      TI J[N][N], x[N];
-      fam.template jacobian<TI>(u, aux, J);
+  // per-lane state
+  int st = ST_IDLE;
+  int64_t s = 0, uo = 0;
+  int32_t k = 0, nf = 0, nj = 0, m = 0;
+  double alpha = 1.0, phi0 = 0.0, Delta = o.delta0;
+  LaneFam<N, FAM> fam;
+  double u[N], F[N], aux[N], d[N];
+  TI dN[N], g[N], dC[N], dd[N];
+  TI nN = 0, ng2 = 0, nJg2 = 0, tC = 0, nC2 = 0, qa = 0, qb = 0;
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = (TI)(-F[i]);
-      ++nj;
-      if (!lane_lu_solve<N, TI>(J, x)) { rc = RC_SINGULAR; break; }
-      double d[N];
+  for (int i = 0; i < N; ++i) { u[i] = F[i] = aux[i] = d[i] = 0.0; dN[i] = g[i] = dC[i] = dd[i] = TI(0); }
+
+  auto finish = [&](int32_t rc, int32_t iters) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) d[i] = (double)x[i];
-      const double phi0 = sumsq<N, double>(F);
-      double alpha = 1.0;
-      bool acc = false;
+    for (int i = 0; i < N; ++i) a.u_out[uo + i] = u[i];
+    a.fnorm[s] = all_finite(F) ? norm_inf(F) : __builtin_inf();
+    a.iters[s] = iters;
+    a.retcode[s] = rc;
+    if (a.nfev) a.nfev[s] = nf;
+    if (a.njev) a.njev[s] = nj;
+    st = ST_IDLE;
+  };
+
+  while (true) {
+    // ---------------- retire / refill ----------------
+    const bool more = chunk < nchunks;
+    if (__any(st == ST_IDLE) && more) {
+      if (buf_wait) {
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_sync();
+        buf_wait = false;
+      }
+      const unsigned long long idle = __ballot(st == ST_IDLE);
+      const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
+      const int take = min(__popcll(idle), buf_cnt - buf_next);
+      const bool fresh = st == ST_IDLE && rank < take;
+      if (fresh) {
+        const int slot = buf_next + rank;
+        const int64_t t = chunk * 64 + slot;
+        s = a.sys ? (int64_t)a.sys[t] : t;
+        uo = a.u_off ? a.u_off[s] : s * N;
+        if (staged) fam.load_lds(stage + slot * P);
+        else fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P));
+#pragma unroll
+        for (int i = 0; i < N; ++i) u[i] = a.u0[uo + i];
+      }
+      buf_next += take;
+      if (buf_next == buf_cnt) {
+        // chunk handed out: once every lane has read its slot, start copying
+        // the next chunk into the same buffer
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_sync();
+        chunk += gridDim.x;
+        buf_next = 0;
+        buf_cnt = chunk < nchunks ? (int)min<int64_t>(64, a.count - chunk * 64) : 0;
+        if (staged && chunk < nchunks) {
+          stage_to_lds(a.params + chunk * 64 * (int64_t)P, stage, (int64_t)buf_cnt * P * 8);
+          buf_wait = true;
+        }
+      }
+      if (fresh) {
+        fam.residual(u, F, aux);
+        nf = 1;
+        nj = 0;
+        k = 0;
+        Delta = o.delta0;
+        st = ST_DIR;
+        if (!all_finite(F)) finish(RC_NONFINITE, 0);
+        else if (norm_inf(F) <= tol) finish(RC_SUCCESS, 0);
+        else if (maxit == 0) finish(RC_MAXITERS, 0);
+      }
+    }
+    if (__all(st == ST_IDLE) && chunk >= nchunks) break;
+
+    // ---------------- direction (lanes that need one) ----------------
+    if (ALG == ALG_DOGLEG && st != ST_IDLE) ++k;  // every trial is an iteration
+    if (__any(st == ST_DIR)) {
+      if (st == ST_DIR) {
+        if (ALG != ALG_DOGLEG) ++k;
+        TI J[N][N];
+        fam.template jacobian<TI>(u, aux, J);
+        ++nj;
+        if (ALG != ALG_DOGLEG) {
+          // J_k delta = -F(u_k)
+          TI x[N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) x[i] = (TI)(-F[i]);
+          if (!lane_lu_solve<N, TI>(J, x)) {
+            finish(RC_SINGULAR, k);
+          } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) d[i] = (double)x[i];
+            alpha = 1.0;
+            m = 0;
+            phi0 = sumsq<N, double>(F);
+            st = ST_TRIAL;
+          }
+        } else {
+          TI Ff[N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) Ff[i] = (TI)F[i];
+          // g = J^T F (steepest-descent direction of 0.5||F||^2), Jg = J g
+          TI Jg[N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            TI sacc = J[0][j] * Ff[0];
+#pragma unroll
+            for (int i = 1; i < N; ++i) sacc = __builtin_fma(J[i][j], Ff[i], sacc);
+            g[j] = sacc;
+          }
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            TI sacc = J[i][0] * g[0];
+#pragma unroll
+            for (int j = 1; j < N; ++j) sacc = __builtin_fma(J[i][j], g[j], sacc);
+            Jg[i] = sacc;
+          }
+#pragma unroll
+          for (int i = 0; i < N; ++i) dN[i] = -Ff[i];
+          if (!lane_lu_solve<N, TI>(J, dN)) {
+            finish(RC_SINGULAR, k);
+          } else {
+            nN = __builtin_sqrt(sumsq<N, TI>(dN));
+            ng2 = sumsq<N, TI>(g);
+            nJg2 = sumsq<N, TI>(Jg);
+            // the Cauchy point and the dogleg segment do not depend on the radius
+            tC = ng2 / nJg2;
+#pragma unroll
+            for (int i = 0; i < N; ++i) dC[i] = -tC * g[i];
+            nC2 = sumsq<N, TI>(dC);
+#pragma unroll
+            for (int i = 0; i < N; ++i) dd[i] = dN[i] - dC[i];
+            qa = sumsq<N, TI>(dd);
+            TI dcd = dC[0] * dd[0];
+#pragma unroll
+            for (int i = 1; i < N; ++i) dcd = __builtin_fma(dC[i], dd[i], dcd);
+            qb = TI(2) * dcd;
+            st = ST_TRIAL;
+          }
+        }
+      }
+    }
+
+    // ---------------- trial point, residual, decision ----------------
+    if (st == ST_TRIAL) {
       double ut[N], Ft[N], auxt[N];
-      for (int m = 0; m <= mh; ++m) {
+      double step[N];
+      double pred = 0.0, phi = 0.0;
+      if (ALG == ALG_NEWTON) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) ut[i] = u[i] + d[i];
+      } else if (ALG == ALG_ARMIJO) {
 #pragma unroll
         for (int i = 0; i < N; ++i) ut[i] = __builtin_fma(alpha, d[i], u[i]);
-        fam.residual(ut, Ft, auxt);
-        ++nf;
-        if (all_finite(Ft) && sumsq<N, double>(Ft) <= (1.0 - c2 * alpha) * phi0) { acc = true; break; }
-        alpha *= rho;
-      }
-      if (!acc) { rc = RC_LINESEARCH_FAILED; break; }
-#pragma unroll
-      for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
-      if (norm_inf(F) <= tol) { rc = RC_SUCCESS; break; }
-    }
-    it = k > maxit ? maxit : k;
-  }
-
-  if (!done && ALG == ALG_DOGLEG) {
-    const DoglegOpts o = a.o.dogleg();
-    double Delta = o.delta0;
-    bool fresh = true;
-    TI dN[N], g[N];
-    TI nN = 0, ng2 = 0, nJg2 = 0, tC = 0, nC2 = 0, qa = 0, qb = 0;
-    TI dC[N], dd[N];
-    int k = 1;
-    for (; k <= maxit; ++k) {
-      if (fresh) {
-        TI J[N][N], Jg[N], Ff[N];
-        fam.template jacobian<TI>(u, aux, J);
-#pragma unroll
-        for (int i = 0; i < N; ++i) Ff[i] = (TI)F[i];
-        // g = J^T F (steepest-descent direction of 0.5||F||^2), Jg = J g
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          TI sacc = J[0][j] * Ff[0];
-#pragma unroll
-          for (int i = 1; i < N; ++i) sacc = __builtin_fma(J[i][j], Ff[i], sacc);
-          g[j] = sacc;
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          TI sacc = J[i][0] * g[0];
-#pragma unroll
-          for (int j = 1; j < N; ++j) sacc = __builtin_fma(J[i][j], g[j], sacc);
-          Jg[i] = sacc;
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) dN[i] = -Ff[i];
-        ++nj;
-        if (!lane_lu_solve<N, TI>(J, dN)) { rc = RC_SINGULAR; break; }
-        nN = __builtin_sqrt(sumsq<N, TI>(dN));
-        ng2 = sumsq<N, TI>(g);
-        nJg2 = sumsq<N, TI>(Jg);
-        // Cauchy point and the dogleg segment do not depend on the radius
-        tC = ng2 / nJg2;
-#pragma unroll
-        for (int i = 0; i < N; ++i) dC[i] = -tC * g[i];
-        nC2 = sumsq<N, TI>(dC);
-#pragma unroll
-        for (int i = 0; i < N; ++i) dd[i] = dN[i] - dC[i];
-        qa = sumsq<N, TI>(dd);
-        TI dcd = dC[0] * dd[0];
-#pragma unroll
-        for (int i = 1; i < N; ++i) dcd = __builtin_fma(dC[i], dd[i], dcd);
-        qb = TI(2) * dcd;
-        fresh = false;
-      }
-      // --- dogleg step for the current radius (step algebra in TI) ---
-      const double phi = sumsq<N, double>(F);
-      double step[N];
-      double pred;
-      const TI D = (TI)Delta;
-      if ((double)nN <= Delta) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) step[i] = (double)dN[i];
-        pred = phi;  // F + J dN = 0
-      } else if (ng2 == TI(0)) {
-        const TI r = D / nN;
-#pragma unroll
-        for (int i = 0; i < N; ++i) step[i] = (double)(dN[i] * r);
-        const double om = 1.0 - (double)r;
-        pred = phi * (1.0 - om * om);  // F + J step = (1 - r) F
-      } else if (__builtin_sqrt(nC2) >= D) {
-        const TI sc = D / __builtin_sqrt(ng2);
-#pragma unroll
-        for (int i = 0; i < N; ++i) step[i] = (double)(-sc * g[i]);
-        // ||F - sc Jg||^2 = phi - 2 sc ||g||^2 + sc^2 ||Jg||^2 since F.Jg = ||g||^2
-        pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
       } else {
-        const TI qc = nC2 - D * D;
-        const TI disc = qb * qb - TI(4) * qa * qc;
-        const TI sq = __builtin_sqrt(disc);
-        const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
+        // dogleg step for the current radius (step algebra in TI)
+        phi = sumsq<N, double>(F);
+        const TI D = (TI)Delta;
+        if ((double)nN <= Delta) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) step[i] = (double)__builtin_fma(tau, dd[i], dC[i]);
-        // F + J step = (1 - tau)(F - tC Jg), ||F - tC Jg||^2 = phi - tC ||g||^2
-        const double om = 1.0 - (double)tau;
-        pred = phi - om * om * (phi - (double)tC * (double)ng2);
+          for (int i = 0; i < N; ++i) step[i] = (double)dN[i];
+          pred = phi;  // F + J dN = 0
+        } else if (ng2 == TI(0)) {
+          const TI r = D / nN;
+#pragma unroll
+          for (int i = 0; i < N; ++i) step[i] = (double)(dN[i] * r);
+          const double om = 1.0 - (double)r;
+          pred = phi * (1.0 - om * om);  // F + J step = (1 - r) F
+        } else if (__builtin_sqrt(nC2) >= D) {
+          const TI sc = D / __builtin_sqrt(ng2);
+#pragma unroll
+          for (int i = 0; i < N; ++i) step[i] = (double)(-sc * g[i]);
+          // ||F - sc Jg||^2 = phi - 2 sc ||g||^2 + sc^2 ||Jg||^2, as F.Jg = ||g||^2
+          pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
+        } else {
+          const TI qc = nC2 - D * D;
+          const TI disc = qb * qb - TI(4) * qa * qc;
+          const TI sq = __builtin_sqrt(disc);
+          const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
+#pragma unroll
+          for (int i = 0; i < N; ++i) step[i] = (double)__builtin_fma(tau, dd[i], dC[i]);
+          // F + J step = (1 - tau)(F - tC Jg), ||F - tC Jg||^2 = phi - tC ||g||^2
+          const double om = 1.0 - (double)tau;
+          pred = phi - om * om * (phi - (double)tC * (double)ng2);
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) ut[i] = u[i] + step[i];
       }
-      double ut[N], Ft[N], auxt[N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) ut[i] = u[i] + step[i];
       fam.residual(ut, Ft, auxt);
       ++nf;
-      const double ared = phi - sumsq<N, double>(Ft);
-      const double rho = (all_finite(Ft) && pred > 0.0) ? ared / pred : -__builtin_inf();
-      bool accept;
-      if (rho >= o.eta2) {
-        accept = true;
-        Delta = fmin(o.expand * Delta, o.delta_max);
-      } else if (rho > o.eta1) {
-        accept = true;
-      } else {
-        accept = false;
-        Delta = o.shrink * __builtin_sqrt(sumsq<N, double>(step));
-      }
-      if (accept) {
+      if (ALG == ALG_NEWTON) {
 #pragma unroll
         for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
-        fresh = true;
-        if (norm_inf(F) <= tol) { rc = RC_SUCCESS; break; }
+        if (!all_finite(F)) finish(RC_NONFINITE, k);
+        else if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+        else if (k >= maxit) finish(RC_MAXITERS, maxit);
+        else st = ST_DIR;
+      } else if (ALG == ALG_ARMIJO) {
+        if (all_finite(Ft) && sumsq<N, double>(Ft) <= (1.0 - c2 * alpha) * phi0) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
+          if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+          else st = ST_DIR;
+        } else {
+          ++m;
+          alpha *= rho_bt;
+          if (m > mh) finish(RC_LINESEARCH_FAILED, k);
+        }
       } else {
-        const double un = __builtin_sqrt(sumsq<N, double>(u));
-        if (Delta < o.collapse * fmax(1.0, un)) { rc = RC_TR_COLLAPSED; break; }
+        const double ared = phi - sumsq<N, double>(Ft);
+        const double rho = (all_finite(Ft) && pred > 0.0) ? ared / pred : -__builtin_inf();
+        bool accept;
+        if (rho >= o.eta2) {
+          accept = true;
+          Delta = fmin(o.expand * Delta, o.delta_max);
+        } else if (rho > o.eta1) {
+          accept = true;
+        } else {
+          accept = false;
+          Delta = o.shrink * __builtin_sqrt(sumsq<N, double>(step));
+        }
+        if (accept) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
+          if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+          else st = ST_DIR;
+        } else {
+          const double un = __builtin_sqrt(sumsq<N, double>(u));
+          if (Delta < o.collapse * fmax(1.0, un)) finish(RC_TR_COLLAPSED, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+        }
       }
     }
-    it = k > maxit ? maxit : k;
   }
-
-#pragma unroll
-  for (int i = 0; i < N; ++i) a.u_out[uo + i] = u[i];
-  a.fnorm[s] = all_finite(F) ? norm_inf(F) : __builtin_inf();
-  a.iters[s] = it;
-  a.retcode[s] = rc;
-  if (a.nfev) a.nfev[s] = nf;
-  if (a.njev) a.njev[s] = nj;
 }
 
 }  // namespace nls
