@@ -61,6 +61,27 @@ def profiled_traffic():
     return int(vals["traffic_bytes_per_launch"])
 
 
+def flops_model(family, alg, n, iters, nfev, njev):
+    """Per-system flop model (+,-,*,/,sqrt count 1, FMA 2; tanh counted as 1).
+    R: residual; J: Jacobian; LU: factorisation; TRSV: the two triangular
+    solves.  Newton/Armijo: every iteration factorises, every residual
+    evaluation after the first is a trial (+4N for forming it and its merit).
+    Dogleg: njev factorising iterations carry J + LU + TRSV + 4N^2 + 22N (the
+    gradient, J g and the step algebra), every iteration one trial residual,
+    and rejected iterations 16N of step algebra."""
+    n = np.asarray(n, dtype=np.float64)
+    R = np.where(family == 0, 2 * n * n + 5 * n, 2 * n * n + 5 * n)  # tanh: 2N^2+4N + N tanh
+    J = np.where(family == 0, 3 * n, n * n + 3 * n)
+    LU = 2 * n ** 3 / 3 - n * n / 2 - n / 6
+    TRSV = 2 * n * n - n
+    iters = np.asarray(iters, dtype=np.float64)
+    nfev = np.asarray(nfev, dtype=np.float64)
+    njev = np.asarray(njev, dtype=np.float64)
+    newton_like = R + njev * (J + LU + TRSV) + (nfev - 1) * (R + 4 * n)
+    dogleg = R + njev * (J + LU + TRSV + 4 * n * n + 22 * n) + (nfev - 1) * R + (iters - njev) * 16 * n
+    return np.where(alg == 2, dogleg, newton_like)
+
+
 def run_form(nls, ctx, db, precision, steps, warmup, with_counters=False):
     import torch
     out = db.alloc_results()
@@ -82,6 +103,55 @@ def run_form(nls, ctx, db, precision, steps, warmup, with_counters=False):
     return out, wall / steps, gpu_ms
 
 
+def extra_workloads(nls, ctx, args):
+    """The tanh N=16 dogleg workload (FP64 and FP32-inner) and the mixed
+    500,000-system batch, each timed like the headline (fewer steps)."""
+    from paper_2403_16341_amd import inputs
+    import torch
+    out = {}
+    for k, name in ((3, "tanh_n16_dogleg_262144"), (4, "mixed_500000")):
+        b = inputs.config(k)
+        db = nls.DeviceBatch(b)
+        torch.cuda.synchronize()
+        entry = {"systems": b.M}
+        for prec, pname in ((inputs.PREC_FP64, "fp64"), (inputs.PREC_FP32_INNER, "fp32_inner")):
+            o, step, gms = run_form(nls, ctx, db, prec, 3, 1, with_counters=True)
+            rc = o["retcode"].cpu().numpy()
+            conv = int((rc == 0).sum())
+            it = o["iters"].cpu().numpy()
+            nf = o["nfev"].cpu().numpy()
+            nj = o["njev"].cpu().numpy()
+            fl = float(flops_model(b.family, b.alg, b.n, it, nf, nj).sum())
+            kms = float(np.mean(gms))
+            e = {"value": conv / step, "unit": "solves/s", "ms_per_step": step * 1e3, "kernel_ms": kms,
+                 "converged": conv, "retcodes": np.bincount(rc, minlength=7).tolist(),
+                 "mean_iters": float(it.mean()), "flops": fl,
+                 "tflops": fl / (kms * 1e-3) / 1e12,
+                 "fp64_vector_frac": fl / (kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+            if pname == "fp64":
+                u64 = o["u"].clone()
+                rc64 = rc
+            else:
+                same = (rc == 0) & (rc64 == 0)
+                du = (o["u"] - u64).abs().cpu().numpy()
+                rel = []
+                uu = u64.cpu().numpy()
+                for s_ in np.nonzero(same)[0][:20000]:
+                    sl = slice(b.u_off[s_], b.u_off[s_ + 1])
+                    rel.append(du[sl].max() / max(np.abs(uu[sl]).max(), 1e-300))
+                rel = np.array(rel) if rel else np.zeros(1)
+                e["rel_diff_vs_fp64_p50"] = float(np.median(rel))
+                e["rel_diff_vs_fp64_max"] = float(rel.max())
+                e["same_retcode_frac"] = float((rc == rc64).mean())
+            entry[pname] = e
+            print("[bench] %s %s: %.3f ms/step, %d converged" % (name, pname, step * 1e3, conv),
+                  file=sys.stderr, flush=True)
+        out[name] = entry
+        del db
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +159,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--systems", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the tanh N=16 and mixed workloads")
     ap.add_argument("--forms", default="fp64,fp32", help="precision forms to time (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
@@ -183,6 +254,9 @@ def main():
                        "p50_rel_diff_vs_fp64": float(np.median(rel))},
         "retcodes_fp64": np.bincount(rc64, minlength=7).tolist(),
     }
+
+    if not args.no_extra:
+        res["workloads"] = extra_workloads(nls, ctx, args)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -32,6 +32,7 @@ GROUP_BUCKETS = (16, 24, 32, 40, 48, 56, 64)
 SOURCES = [
     # (file, is_device)
     ("nls_host.cpp", False),
+    ("nls_util.hip", True),
     ("nls_lane_f64.hip", True),
     ("nls_lane_f32.hip", True),
 ] + [("nls_group_%s_nb%d.hip" % (p, nb), True) for p in ("f64", "f32") for nb in GROUP_BUCKETS]

@@ -54,6 +54,10 @@ struct nls_context {
   uint64_t next_ticket = 1;
   std::unordered_map<uint64_t, Ticket> tickets;
   uint64_t held_bytes = 0;  // device bytes held by outstanding tickets
+  // dynamic work counters, one per launch of a call; calls on one stream run
+  // in order, so every call may reuse them (zeroed at its start)
+  int64_t* counters = nullptr;
+  int ncounters = 0;
 };
 
 namespace {
@@ -271,6 +275,13 @@ int nls_create(const nls_context_desc* d, nls_context** out) {
     }
     c->own_stream = true;
   }
+  c->ncounters = 512;
+  e = hipMalloc((void**)&c->counters, sizeof(int64_t) * c->ncounters);
+  if (e != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return hip_fail(nullptr, e, "hipMalloc(counters)");
+  }
   *out = c;
   return NLS_OK;
 }
@@ -290,6 +301,7 @@ int nls_destroy(nls_context* c) {
   hipStreamSynchronize(c->stream);
   for (auto& kv : c->tickets) release_ticket(kv.second, c);
   c->tickets.clear();
+  if (c->counters) hipFree(c->counters);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return NLS_OK;
@@ -422,10 +434,12 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   base.o = to_kopts(opts);
 
   if (M > 0 && uniform) {
+    if (int z = launch_zero_counters(c->counters, 1, c->stream); z < 0) return bail((hipError_t)(-z), "zero counters");
     KArgs a = base;
     a.count = M;
     a.P = P0;
     a.n = n0;
+    a.counter = c->counters;
     const bool lane = lane_mapped(n0);
     int rcode = launch(lane ? n0 : group_bucket(n0), lane, fam0, alg0, b->precision, a, c->stream);
     if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
@@ -470,7 +484,11 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     if ((e = hipMemcpyAsync(dn, nn.data(), M, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
       return bail(e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+    if ((int)buckets.size() > c->ncounters) return fail(c, NLS_E_INVALID, "too many buckets");
+    if (int z = launch_zero_counters(c->counters, (int)buckets.size(), c->stream); z < 0)
+      return bail((hipError_t)(-z), "zero counters");
     int64_t at = 0;
+    int bi = 0;
     for (auto& kv : buckets) {
       const int64_t key = kv.first;
       const bool lane = ((key >> 40) & 1) == 0;
@@ -485,6 +503,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       a.count = (int64_t)kv.second.size();
       a.P = 0;
       a.n = key_n;
+      a.counter = c->counters + bi++;
       int rcode = launch(key_n, lane, fam, alg, b->precision, a, c->stream);
       if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
       if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "nls_types.h"
 
 namespace nls {
@@ -92,7 +94,6 @@ template <int N, int FAM> struct LaneFam;
 template <int N> struct LaneFam<N, FAM_CUBIC> {
   double A[N][N];
   double b[N];
-  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -128,7 +129,6 @@ template <int N> struct LaneFam<N, FAM_TANH> {
   double A[N][N];
   double b[N];
   double beta;
-  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -167,7 +167,6 @@ template <int N> struct LaneFam<N, FAM_TANH> {
 };
 
 template <int N> struct LaneFam<N, FAM_ROSENBROCK> {
-  __device__ __forceinline__ void load_lds(const double*) {}
   __device__ __forceinline__ void load(const double* __restrict__) {}
   __device__ __forceinline__ void residual(const double (&u)[N], double (&F)[N], double (&aux)[N]) const {
     F[0] = 1.0 - u[0];
@@ -200,7 +199,6 @@ template <int N> struct LaneFam<N, FAM_ROSENBROCK> {
 template <int N> struct LaneFam<N, FAM_PAPER> {
   static_assert(N == 2, "the workflow example has two unknowns");
   double a, b, c;
-  __device__ __forceinline__ void load_lds(const double* p) { load(p); }
   __device__ __forceinline__ void load(const double* __restrict__ p) {
     a = p[0];
     b = p[1];
@@ -229,6 +227,23 @@ template <int N> struct LaneFam<N, FAM_PAPER> {
   }
 };
 
+// Reciprocal for pivots: the hardware estimate refined by Newton-Raphson
+// (e = 1 - x r, r += r e; two steps in FP64, one in FP32) -- within an ulp or
+// two of 1/x for every finite non-zero x whose reciprocal is a normal number.
+// Zero and non-finite pivots never reach it (they end the factorisation).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
 // ---------------------------------------------------------------------------
 // Lane LU with partial pivoting, RHS carried along (forward substitution is
 // applied while eliminating), then back substitution.  Returns false on a
@@ -239,19 +254,31 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    // first maximum of |a_ik|, i >= k, in current row order
-    T best = __builtin_fabs(a[k][k]);
-    int p = k;
+    // Pivot: the first maximum of |a_ik|, i >= k, in current row order.  Row k
+    // keeps the pivot unless some later |a_ik| is strictly larger than |a_kk|
+    // (one compare per candidate); the full running-maximum search runs only
+    // when that happens on some lane of the wavefront.
+    const T dkk = __builtin_fabs(a[k][k]);
+    bool larger = false;
 #pragma unroll
-    for (int i = k + 1; i < N; ++i) {
-      T v = __builtin_fabs(a[i][k]);
-      bool c = v > best;
-      best = c ? v : best;
-      p = c ? i : p;
+    for (int i = k + 1; i < N; ++i) larger = larger || (__builtin_fabs(a[i][k]) > dkk);
+    int p = k;
+    if (__any(larger)) {
+      __asm__ volatile("" ::: "memory");
+      T best = dkk;
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) {
+        T v = __builtin_fabs(a[i][k]);
+        bool c = v > best;
+        best = c ? v : best;
+        p = c ? i : p;
+      }
     }
     // exchange rows k and p (columns k.. and the RHS) with selects; the whole
-    // network is skipped when no lane of the wavefront needs an exchange
+    // network is skipped when no lane of the wavefront needs an exchange (the
+    // empty asm keeps the compiler from turning the branch into selects)
     if (__any(p != k)) {
+      __asm__ volatile("" ::: "memory");
 #pragma unroll
       for (int i = k + 1; i < N; ++i) {
         const bool sel = (p == i);
@@ -268,7 +295,7 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
     }
     const T piv = a[k][k];
     ok = ok && (piv != T(0)) && fin(piv);
-    const T r = T(1) / piv;
+    const T r = recip(piv);
     a[k][k] = r;  // the pivot is only needed as its reciprocal from here on
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
@@ -328,23 +355,69 @@ template <int N, int FAM> struct LaneParams {
 
 enum : int { ST_IDLE = 0, ST_DIR = 1, ST_TRIAL = 2 };
 
-// copy `bytes` (a multiple of 8) from global memory into LDS, 16 bytes per
-// lane per instruction and a 4-byte-granule tail; asynchronous until the next
-// s_waitcnt
-__device__ __forceinline__ void stage_to_lds(const double* __restrict__ src, double* dst, int64_t bytes) {
-  const int lane = threadIdx.x;
+// Chunk staging.  Lane l copies the P parameters and the N starting values of
+// system l of the chunk from global memory into LDS "column" l: a region of
+// K doubles is laid out as 16-byte granules (granule g of lane l at byte
+// g * 1024 + l * 16) when K is even, else as 4-byte words (word w at
+// w * 256 + l * 4), so that a lane later reads any slot's values without LDS
+// bank conflicts.  The copies are asynchronous until the next s_waitcnt.
+template <int K> struct StageRegion {
+  static constexpr bool X4 = (K % 2) == 0;
+  static constexpr int BYTES = K <= 0 ? 0 : (X4 ? (K / 2) * 1024 : 2 * K * 256);
+};
+template <int P, int N> struct StageLayout {
+  static constexpr int U0_OFFSET = StageRegion<P>::BYTES;  // bytes
+  static constexpr int BYTES = StageRegion<P>::BYTES + StageRegion<N>::BYTES;
+  static constexpr int DOUBLES = BYTES / 8 > 0 ? BYTES / 8 : 1;
+};
+
+typedef __attribute__((address_space(3))) char lds_char;
+
+template <int K>
+__device__ __forceinline__ void stage_region(const double* __restrict__ src, lds_char* l) {
   const char* g = reinterpret_cast<const char*>(src);
-  char* l = reinterpret_cast<char*>(dst);
-  const int64_t full = bytes & ~int64_t(1023);
-  for (int64_t off = 0; off < full; off += 1024) {
-    __builtin_amdgcn_global_load_lds(g + off + lane * 16,
-                                     (__attribute__((address_space(3))) void*)(l + off), 16, 0, 0);
+  if (StageRegion<K>::X4) {
+#pragma unroll
+    for (int e = 0; e < K / 2; ++e)
+      __builtin_amdgcn_global_load_lds(g + e * 16, (__attribute__((address_space(3))) void*)(l + e * 1024),
+                                       16, 0, 0);
+  } else {
+#pragma unroll
+    for (int w = 0; w < 2 * K; ++w)
+      __builtin_amdgcn_global_load_lds(g + w * 4, (__attribute__((address_space(3))) void*)(l + w * 256),
+                                       4, 0, 0);
   }
-  // remainder (a multiple of 8 bytes): 4 bytes per lane per instruction
-  for (int64_t off = full; off < bytes; off += 256) {
-    if (off + lane * 4 < bytes)
-      __builtin_amdgcn_global_load_lds(g + off + lane * 4,
-                                       (__attribute__((address_space(3))) void*)(l + off), 4, 0, 0);
+}
+
+// stage systems first .. first+cnt-1 (lane l takes system first + l); `l` is
+// the staging buffer as an LDS-space pointer
+template <int P, int N>
+__device__ __forceinline__ void stage_chunk(const double* __restrict__ params, const double* __restrict__ u0,
+                                            int64_t first, lds_char* l, int cnt) {
+  const int lane = threadIdx.x;
+  if (lane >= cnt) return;
+  stage_region<P>(params + (first + lane) * P, l);
+  stage_region<N>(u0 + (first + lane) * N, l + StageLayout<P, N>::U0_OFFSET);
+}
+
+template <int K>
+__device__ __forceinline__ void unstage_region(const char* l, int slot, double (&v)[K]) {
+  if (StageRegion<K>::X4) {
+    const double2* st2 = reinterpret_cast<const double2*>(l);
+#pragma unroll
+    for (int e = 0; e < K / 2; ++e) {
+      const double2 x = st2[e * 64 + slot];
+      v[2 * e] = x.x;
+      v[2 * e + 1] = x.y;
+    }
+  } else {
+    const uint32_t* st4 = reinterpret_cast<const uint32_t*>(l);
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const uint32_t lo = st4[(2 * e) * 64 + slot];
+      const uint32_t hi = st4[(2 * e + 1) * 64 + slot];
+      v[e] = __hiloint2double((int)hi, (int)lo);
+    }
   }
 }
 
@@ -352,10 +425,14 @@ template <int N, int FAM, int ALG, typename TI>
 __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   constexpr int P = LaneParams<N, FAM>::P;
   constexpr int PS = P > 0 ? P : 1;
-  __shared__ __attribute__((aligned(16))) double stage[64 * PS];
+  __shared__ __attribute__((aligned(16))) double stage[StageLayout<PS, N>::DOUBLES];
+  lds_char* const stage_lds = (lds_char*)stage;
 
   const int lane = threadIdx.x;
-  const bool staged = P > 0 && a.sys == nullptr && a.p_off == nullptr;
+  // staging needs packed systems and, for 16-byte granules, 16-byte aligned bases
+  const bool staged = P > 0 && a.sys == nullptr && a.p_off == nullptr && a.u_off == nullptr &&
+                      (!StageRegion<PS>::X4 || (reinterpret_cast<uintptr_t>(a.params) & 15) == 0) &&
+                      (!StageRegion<N>::X4 || (reinterpret_cast<uintptr_t>(a.u0) & 15) == 0);
   const int64_t nchunks = (a.count + 63) / 64;
   const double tol = a.abstol;
   const int32_t maxit = a.maxiters;
@@ -364,14 +441,21 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   const int32_t mh = a.o.armijo_max_halvings;
   const DoglegOpts o = a.o.dogleg();
 
-  // chunk currently being handed out (wave-uniform)
-  int64_t chunk = blockIdx.x;
+  // chunk currently being handed out (wave-uniform): from the device-wide
+  // counter when there is one, else blockIdx.x, blockIdx.x + gridDim.x, ...
+  auto next_chunk = [&](int64_t cur) -> int64_t {
+    if (!a.counter) return cur + gridDim.x;
+    int64_t c = 0;
+    if (lane == 0) c = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(a.counter), 1ull);
+    return __shfl(c, 0, 64);
+  };
+  int64_t chunk = a.counter ? next_chunk(0) : (int64_t)blockIdx.x;
   int buf_next = 0, buf_cnt = 0;
   bool buf_wait = false;
   if (chunk < nchunks) {
     buf_cnt = (int)min<int64_t>(64, a.count - chunk * 64);
     if (staged) {
-      stage_to_lds(a.params + chunk * 64 * (int64_t)P, stage, (int64_t)buf_cnt * P * 8);
+      stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
       buf_wait = true;
     }
   }
@@ -381,6 +465,9 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   int64_t s = 0, uo = 0;
   int32_t k = 0, nf = 0, nj = 0, m = 0;
   double alpha = 1.0, phi0 = 0.0, Delta = o.delta0;
+  // ||F||_inf (+inf if F is not finite) and ||F||_2^2 of the current iterate,
+  // kept so that F itself need not stay live across a factorisation
+  double fcur = 0.0, phi = 0.0;
   LaneFam<N, FAM> fam;
   double u[N], F[N], aux[N], d[N];
   TI dN[N], g[N], dC[N], dd[N];
@@ -391,7 +478,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   auto finish = [&](int32_t rc, int32_t iters) {
 #pragma unroll
     for (int i = 0; i < N; ++i) a.u_out[uo + i] = u[i];
-    a.fnorm[s] = all_finite(F) ? norm_inf(F) : __builtin_inf();
+    a.fnorm[s] = fcur;
     a.iters[s] = iters;
     a.retcode[s] = rc;
     if (a.nfev) a.nfev[s] = nf;
@@ -418,10 +505,17 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         const int64_t t = chunk * 64 + slot;
         s = a.sys ? (int64_t)a.sys[t] : t;
         uo = a.u_off ? a.u_off[s] : s * N;
-        if (staged) fam.load_lds(stage + slot * P);
-        else fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P));
+        if (staged) {
+          double pv[PS];
+          const char* l = reinterpret_cast<const char*>(stage);
+          unstage_region<PS>(l, slot, pv);
+          fam.load(pv);
+          unstage_region<N>(l + StageLayout<PS, N>::U0_OFFSET, slot, u);
+        } else {
+          fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P));
 #pragma unroll
-        for (int i = 0; i < N; ++i) u[i] = a.u0[uo + i];
+          for (int i = 0; i < N; ++i) u[i] = a.u0[uo + i];
+        }
       }
       buf_next += take;
       if (buf_next == buf_cnt) {
@@ -429,11 +523,11 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         // the next chunk into the same buffer
         __builtin_amdgcn_s_waitcnt(0);
         wave_sync();
-        chunk += gridDim.x;
+        chunk = next_chunk(chunk);
         buf_next = 0;
         buf_cnt = chunk < nchunks ? (int)min<int64_t>(64, a.count - chunk * 64) : 0;
         if (staged && chunk < nchunks) {
-          stage_to_lds(a.params + chunk * 64 * (int64_t)P, stage, (int64_t)buf_cnt * P * 8);
+          stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
           buf_wait = true;
         }
       }
@@ -444,8 +538,11 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         k = 0;
         Delta = o.delta0;
         st = ST_DIR;
-        if (!all_finite(F)) finish(RC_NONFINITE, 0);
-        else if (norm_inf(F) <= tol) finish(RC_SUCCESS, 0);
+        const bool fin0 = all_finite(F);
+        fcur = fin0 ? norm_inf(F) : __builtin_inf();
+        phi = sumsq<N, double>(F);
+        if (!fin0) finish(RC_NONFINITE, 0);
+        else if (fcur <= tol) finish(RC_SUCCESS, 0);
         else if (maxit == 0) finish(RC_MAXITERS, 0);
       }
     }
@@ -471,7 +568,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
             for (int i = 0; i < N; ++i) d[i] = (double)x[i];
             alpha = 1.0;
             m = 0;
-            phi0 = sumsq<N, double>(F);
+            phi0 = phi;
             st = ST_TRIAL;
           }
         } else {
@@ -524,7 +621,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
     if (st == ST_TRIAL) {
       double ut[N], Ft[N], auxt[N];
       double step[N];
-      double pred = 0.0, phi = 0.0;
+      double pred = 0.0;
       if (ALG == ALG_NEWTON) {
 #pragma unroll
         for (int i = 0; i < N; ++i) ut[i] = u[i] + d[i];
@@ -533,7 +630,6 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         for (int i = 0; i < N; ++i) ut[i] = __builtin_fma(alpha, d[i], u[i]);
       } else {
         // dogleg step for the current radius (step algebra in TI)
-        phi = sumsq<N, double>(F);
         const TI D = (TI)Delta;
         if ((double)nN <= Delta) {
 #pragma unroll
@@ -570,15 +666,21 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       if (ALG == ALG_NEWTON) {
 #pragma unroll
         for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
-        if (!all_finite(F)) finish(RC_NONFINITE, k);
-        else if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+        const bool fin1 = all_finite(F);
+        fcur = fin1 ? norm_inf(F) : __builtin_inf();
+        phi = sumsq<N, double>(F);
+        if (!fin1) finish(RC_NONFINITE, k);
+        else if (fcur <= tol) finish(RC_SUCCESS, k);
         else if (k >= maxit) finish(RC_MAXITERS, maxit);
         else st = ST_DIR;
       } else if (ALG == ALG_ARMIJO) {
-        if (all_finite(Ft) && sumsq<N, double>(Ft) <= (1.0 - c2 * alpha) * phi0) {
+        const double phit = sumsq<N, double>(Ft);
+        if (all_finite(Ft) && phit <= (1.0 - c2 * alpha) * phi0) {
 #pragma unroll
           for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
-          if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+          fcur = norm_inf(F);
+          phi = phit;
+          if (fcur <= tol) finish(RC_SUCCESS, k);
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
           else st = ST_DIR;
         } else {
@@ -587,7 +689,8 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           if (m > mh) finish(RC_LINESEARCH_FAILED, k);
         }
       } else {
-        const double ared = phi - sumsq<N, double>(Ft);
+        const double phit = sumsq<N, double>(Ft);
+        const double ared = phi - phit;
         const double rho = (all_finite(Ft) && pred > 0.0) ? ared / pred : -__builtin_inf();
         bool accept;
         if (rho >= o.eta2) {
@@ -602,7 +705,9 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         if (accept) {
 #pragma unroll
           for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
-          if (norm_inf(F) <= tol) finish(RC_SUCCESS, k);
+          fcur = norm_inf(F);
+          phi = phit;
+          if (fcur <= tol) finish(RC_SUCCESS, k);
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
           else st = ST_DIR;
         } else {
@@ -657,6 +762,10 @@ template <int NB, int L, typename TI> struct GroupShared {
 template <int NB, int L, typename TI> struct GroupSharedT {
   static constexpr int G = 64 / L;
   TI t[G][L][NB];        // products J_ij F_i for the column sums of J^T F
+};
+// algorithms without a gradient need no transpose buffer
+template <int NB, int L> struct GroupSharedT<NB, L, char> {
+  char t[1];
 };
 
 template <int NB, int FAM> struct RowFam;
@@ -799,7 +908,7 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
       wave_sync();
       const TI pv = sh.piv[gi][k];
       ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
-      const TI rp = TI(1) / pv;
+      const TI rp = recip(pv);
       // exchange of logical positions k <-> kp
       if (pos == kp) myrd = rp;
       if (pos == kp) pos = k;
@@ -827,93 +936,116 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
   return ok;
 }
 
+// Persistent group-mapping kernel.  Each group of L lanes solves one system at
+// a time and, when it finishes, takes the next system from a device-wide
+// counter (a.counter, zeroed before the launch) or, without a counter, the
+// next one of its static stride.  Every trip runs the factorisation for the
+// groups that need a new direction, then one residual evaluation for every
+// group holding a trial point; groups diverge freely, and all cross-lane
+// traffic stays inside a group.
 template <int NB, int L, int FAM, int ALG, typename TI>
 __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   constexpr int G = 64 / L;
   __shared__ GroupShared<NB, L, TI> sh;
+  __shared__ GroupSharedT<NB, L, typename std::conditional<ALG == ALG_DOGLEG, TI, char>::type> st;
   const int lane = threadIdx.x;
   const int gi = lane / L;
   const int r = lane % L;
-  const int64_t t = (int64_t)blockIdx.x * G + gi;
-  if (t >= a.count) return;  // whole group leaves together
-  const int64_t s = a.sys ? (int64_t)a.sys[t] : t;
-  const int n = a.nsys ? (int)a.nsys[s] : a.n;
-  const bool own = r < n;
-  const double* __restrict__ p = a.params + (a.p_off ? a.p_off[s] : s * a.P);
-  const int64_t uo = a.u_off ? a.u_off[s] : s * (int64_t)n;
-
-  RowFam<NB, FAM> fam;
-  fam.load(p, n, r, own);
-  double u = own ? a.u0[uo + r] : 0.0;
-  double aux = 0.0;
-  double F = fam.template residual<L, TI>(sh, gi, r, own, u, aux);
-
-  int32_t rc = RC_MAXITERS, it = 0, nf = 1, nj = 0;
   const double tol = a.abstol;
   const int32_t maxit = a.maxiters;
-  bool done = true;
-  if (grp_any<L>(!finite64(F))) {
-    rc = RC_NONFINITE;
-  } else if (grp_max<L>(__builtin_fabs(F)) <= tol) {
-    rc = RC_SUCCESS;
-  } else {
-    done = false;
-  }
+  const double c2 = 2.0 * a.o.armijo_c;
+  const double rho_bt = a.o.armijo_rho;
+  const int32_t mh = a.o.armijo_max_halvings;
+  const DoglegOpts o = a.o.dogleg();
+  const int64_t total_groups = (int64_t)gridDim.x * G;
+  int64_t next_static = (int64_t)blockIdx.x * G + gi;
 
-  if (!done && (ALG == ALG_NEWTON || ALG == ALG_ARMIJO)) {
-    const double c2 = 2.0 * a.o.armijo_c;
-    const double rho = a.o.armijo_rho;
-    const int32_t mh = a.o.armijo_max_halvings;
-    int k = 1;
-    for (; k <= maxit; ++k) {
+  // per-group state (every lane of a group holds the same copy)
+  int gst = ST_IDLE;
+  bool exhausted = false;
+  int64_t s = 0, uo = 0;
+  int n = 0;
+  int32_t k = 0, nf = 0, nj = 0, m = 0;
+  double alpha = 1.0, phi0 = 0.0, Delta = o.delta0, fcur = 0.0, phi = 0.0;
+  TI nN = 0, ng2 = 0, nJg2 = 0, tC = 0, nC2 = 0, qa = 0, qb = 0;
+  // per-lane components (row / component r)
+  bool own = false;
+  RowFam<NB, FAM> fam;
+  double u = 0.0, F = 0.0, aux = 0.0, d = 0.0;
+  TI dN = 0, g = 0, dC = 0, dd = 0;
+
+  auto finish = [&](int32_t rc, int32_t iters) {
+    if (own) a.u_out[uo + r] = u;
+    if (r == 0) {
+      a.fnorm[s] = fcur;
+      a.iters[s] = iters;
+      a.retcode[s] = rc;
+      if (a.nfev) a.nfev[s] = nf;
+      if (a.njev) a.njev[s] = nj;
+    }
+    gst = ST_IDLE;
+  };
+  auto set_norms = [&]() {
+    const bool fin_ = !grp_any<L>(!finite64(F));
+    fcur = fin_ ? grp_max<L>(__builtin_fabs(F)) : __builtin_inf();
+    phi = grp_sum<L>(F * F);
+    return fin_;
+  };
+
+  while (true) {
+    // ---------------- retire / refill (idle groups) ----------------
+    if (gst == ST_IDLE && !exhausted) {
+      int64_t t;
+      if (a.counter) {
+        int64_t mine = 0;
+        if (r == 0) mine = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(a.counter), 1ull);
+        t = __shfl(mine, gi * L, 64);
+      } else {
+        t = next_static;
+        next_static += total_groups;
+      }
+      if (t >= a.count) {
+        exhausted = true;
+      } else {
+        s = a.sys ? (int64_t)a.sys[t] : t;
+        n = a.nsys ? (int)a.nsys[s] : a.n;
+        own = r < n;
+        uo = a.u_off ? a.u_off[s] : s * (int64_t)n;
+        fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P), n, r, own);
+        u = own ? a.u0[uo + r] : 0.0;
+        F = fam.template residual<L, TI>(sh, gi, r, own, u, aux);
+        nf = 1;
+        nj = 0;
+        k = 0;
+        Delta = o.delta0;
+        gst = ST_DIR;
+        const bool fin0 = set_norms();
+        if (!fin0) finish(RC_NONFINITE, 0);
+        else if (fcur <= tol) finish(RC_SUCCESS, 0);
+        else if (maxit == 0) finish(RC_MAXITERS, 0);
+      }
+    }
+    if (!__any(!(gst == ST_IDLE && exhausted))) break;
+
+    // ---------------- direction (groups that need one) ----------------
+    if (ALG == ALG_DOGLEG && gst != ST_IDLE) ++k;  // every trial is an iteration
+    if (gst == ST_DIR) {
+      if (ALG != ALG_DOGLEG) ++k;
       TI J[NB];
       fam.template jacobian_row<L, TI>(sh, gi, r, own, u, aux, J);
       ++nj;
-      if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, (TI)(-F))) { rc = RC_SINGULAR; break; }
-      const double d = own ? (double)sh.sol[gi][r] : 0.0;
-      wave_sync();
-      if (ALG == ALG_NEWTON) {
-        u += d;
-        F = fam.template residual<L, TI>(sh, gi, r, own, u, aux);
-        ++nf;
-        if (grp_any<L>(!finite64(F))) { rc = RC_NONFINITE; break; }
-        if (grp_max<L>(__builtin_fabs(F)) <= tol) { rc = RC_SUCCESS; break; }
-      } else {
-        const double phi0 = grp_sum<L>(F * F);
-        double alpha = 1.0;
-        bool acc = false;
-        double ut = u, Ft = F, auxt = aux;
-        for (int m = 0; m <= mh; ++m) {
-          ut = __builtin_fma(alpha, d, u);
-          Ft = fam.template residual<L, TI>(sh, gi, r, own, ut, auxt);
-          ++nf;
-          const bool fin_t = !grp_any<L>(!finite64(Ft));
-          const double phit = grp_sum<L>(Ft * Ft);
-          if (fin_t && phit <= (1.0 - c2 * alpha) * phi0) { acc = true; break; }
-          alpha *= rho;
+      if constexpr (ALG != ALG_DOGLEG) {
+        if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, (TI)(-F))) {
+          finish(RC_SINGULAR, k);
+        } else {
+          d = own ? (double)sh.sol[gi][r] : 0.0;
+          wave_sync();
+          alpha = 1.0;
+          m = 0;
+          phi0 = phi;
+          gst = ST_TRIAL;
         }
-        if (!acc) { rc = RC_LINESEARCH_FAILED; break; }
-        u = ut;
-        F = Ft;
-        aux = auxt;
-        if (grp_max<L>(__builtin_fabs(F)) <= tol) { rc = RC_SUCCESS; break; }
-      }
-    }
-    it = k > maxit ? maxit : k;
-  }
-
-  if (!done && ALG == ALG_DOGLEG) {
-    __shared__ GroupSharedT<NB, L, TI> st;
-    const DoglegOpts o = a.o.dogleg();
-    double Delta = o.delta0;
-    bool fresh = true;
-    TI dN = 0, g = 0, dC = 0, dd = 0;
-    TI nN = 0, ng2 = 0, nJg2 = 0, tC = 0, nC2 = 0, qa = 0, qb = 0;
-    int k = 1;
-    for (; k <= maxit; ++k) {
-      if (fresh) {
-        TI J[NB];
-        fam.template jacobian_row<L, TI>(sh, gi, r, own, u, aux, J);
+      } else {
         const TI Ff = (TI)F;
         // g_j = sum_i J_ij F_i: row products through LDS, column sums in row order
 #pragma unroll
@@ -932,86 +1064,114 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
         for (int j = 1; j < NB; ++j) jg = __builtin_fma(J[j], sh.gv[gi][j], jg);
         const TI Jg = own ? jg : TI(0);
         wave_sync();
-        ++nj;
-        if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, -Ff)) { rc = RC_SINGULAR; break; }
-        dN = own ? sh.sol[gi][r] : TI(0);
-        wave_sync();
-        nN = __builtin_sqrt(grp_sum<L>(dN * dN));
-        ng2 = grp_sum<L>(g * g);
-        nJg2 = grp_sum<L>(Jg * Jg);
-        tC = ng2 / nJg2;
-        dC = -tC * g;
-        nC2 = grp_sum<L>(dC * dC);
-        dd = dN - dC;
-        qa = grp_sum<L>(dd * dd);
-        qb = TI(2) * grp_sum<L>(dC * dd);
-        fresh = false;
+        if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, -Ff)) {
+          finish(RC_SINGULAR, k);
+        } else {
+          dN = own ? sh.sol[gi][r] : TI(0);
+          wave_sync();
+          nN = __builtin_sqrt(grp_sum<L>(dN * dN));
+          ng2 = grp_sum<L>(g * g);
+          nJg2 = grp_sum<L>(Jg * Jg);
+          tC = ng2 / nJg2;
+          dC = -tC * g;
+          nC2 = grp_sum<L>(dC * dC);
+          dd = dN - dC;
+          qa = grp_sum<L>(dd * dd);
+          qb = TI(2) * grp_sum<L>(dC * dd);
+          gst = ST_TRIAL;
+        }
       }
-      const double phi = grp_sum<L>(F * F);
-      double step, pred;
-      const TI D = (TI)Delta;
-      if ((double)nN <= Delta) {
-        step = (double)dN;
-        pred = phi;
-      } else if (ng2 == TI(0)) {
-        const TI rr = D / nN;
-        step = (double)(dN * rr);
-        const double om = 1.0 - (double)rr;
-        pred = phi * (1.0 - om * om);
-      } else if (__builtin_sqrt(nC2) >= D) {
-        const TI sc = D / __builtin_sqrt(ng2);
-        step = (double)(-sc * g);
-        pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
+    }
+
+    // ---------------- trial point, residual, decision ----------------
+    if (gst == ST_TRIAL) {
+      double ut, step = 0.0, pred = 0.0;
+      if (ALG == ALG_NEWTON) {
+        ut = u + d;
+      } else if (ALG == ALG_ARMIJO) {
+        ut = __builtin_fma(alpha, d, u);
       } else {
-        const TI qc = nC2 - D * D;
-        const TI disc = qb * qb - TI(4) * qa * qc;
-        const TI sq = __builtin_sqrt(disc);
-        const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
-        step = (double)__builtin_fma(tau, dd, dC);
-        const double om = 1.0 - (double)tau;
-        pred = phi - om * om * (phi - (double)tC * (double)ng2);
+        const TI D = (TI)Delta;
+        if ((double)nN <= Delta) {
+          step = (double)dN;
+          pred = phi;
+        } else if (ng2 == TI(0)) {
+          const TI rr = D / nN;
+          step = (double)(dN * rr);
+          const double om = 1.0 - (double)rr;
+          pred = phi * (1.0 - om * om);
+        } else if (__builtin_sqrt(nC2) >= D) {
+          const TI sc = D / __builtin_sqrt(ng2);
+          step = (double)(-sc * g);
+          pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
+        } else {
+          const TI qc = nC2 - D * D;
+          const TI disc = qb * qb - TI(4) * qa * qc;
+          const TI sq = __builtin_sqrt(disc);
+          const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
+          step = (double)__builtin_fma(tau, dd, dC);
+          const double om = 1.0 - (double)tau;
+          pred = phi - om * om * (phi - (double)tC * (double)ng2);
+        }
+        if (!own) step = 0.0;
+        ut = u + step;
       }
-      if (!own) step = 0.0;
-      const double ut = u + step;
       double auxt = 0.0;
       const double Ft = fam.template residual<L, TI>(sh, gi, r, own, ut, auxt);
       ++nf;
       const bool fin_t = !grp_any<L>(!finite64(Ft));
-      const double ared = phi - grp_sum<L>(Ft * Ft);
-      const double rho = (fin_t && pred > 0.0) ? ared / pred : -__builtin_inf();
-      bool accept;
-      if (rho >= o.eta2) {
-        accept = true;
-        Delta = fmin(o.expand * Delta, o.delta_max);
-      } else if (rho > o.eta1) {
-        accept = true;
-      } else {
-        accept = false;
-        Delta = o.shrink * __builtin_sqrt(grp_sum<L>(step * step));
-      }
-      if (accept) {
+      const double phit = grp_sum<L>(Ft * Ft);
+      if (ALG == ALG_NEWTON) {
         u = ut;
         F = Ft;
         aux = auxt;
-        fresh = true;
-        if (grp_max<L>(__builtin_fabs(F)) <= tol) { rc = RC_SUCCESS; break; }
+        const bool fin1 = set_norms();
+        if (!fin1) finish(RC_NONFINITE, k);
+        else if (fcur <= tol) finish(RC_SUCCESS, k);
+        else if (k >= maxit) finish(RC_MAXITERS, maxit);
+        else gst = ST_DIR;
+      } else if (ALG == ALG_ARMIJO) {
+        if (fin_t && phit <= (1.0 - c2 * alpha) * phi0) {
+          u = ut;
+          F = Ft;
+          aux = auxt;
+          set_norms();
+          if (fcur <= tol) finish(RC_SUCCESS, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+          else gst = ST_DIR;
+        } else {
+          ++m;
+          alpha *= rho_bt;
+          if (m > mh) finish(RC_LINESEARCH_FAILED, k);
+        }
       } else {
-        const double un = __builtin_sqrt(grp_sum<L>(u * u));
-        if (Delta < o.collapse * fmax(1.0, un)) { rc = RC_TR_COLLAPSED; break; }
+        const double ared = phi - phit;
+        const double rho = (fin_t && pred > 0.0) ? ared / pred : -__builtin_inf();
+        bool accept;
+        if (rho >= o.eta2) {
+          accept = true;
+          Delta = fmin(o.expand * Delta, o.delta_max);
+        } else if (rho > o.eta1) {
+          accept = true;
+        } else {
+          accept = false;
+          Delta = o.shrink * __builtin_sqrt(grp_sum<L>(step * step));
+        }
+        if (accept) {
+          u = ut;
+          F = Ft;
+          aux = auxt;
+          set_norms();
+          if (fcur <= tol) finish(RC_SUCCESS, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+          else gst = ST_DIR;
+        } else {
+          const double un = __builtin_sqrt(grp_sum<L>(u * u));
+          if (Delta < o.collapse * fmax(1.0, un)) finish(RC_TR_COLLAPSED, k);
+          else if (k >= maxit) finish(RC_MAXITERS, maxit);
+        }
       }
     }
-    it = k > maxit ? maxit : k;
-  }
-
-  if (own) a.u_out[uo + r] = u;
-  const bool finF = !grp_any<L>(!finite64(F));
-  const double fn = grp_max<L>(__builtin_fabs(F));
-  if (r == 0) {
-    a.fnorm[s] = finF ? fn : __builtin_inf();
-    a.iters[s] = it;
-    a.retcode[s] = rc;
-    if (a.nfev) a.nfev[s] = nf;
-    if (a.njev) a.njev[s] = nj;
   }
 }
 

@@ -21,6 +21,9 @@ int launch_lane_f32(int n, int fam, int alg, const KArgs& a, hipStream_t st);
 NLS_DECL_GROUPS(f64)
 NLS_DECL_GROUPS(f32)
 
+// zero `count` work counters on the stream
+int launch_zero_counters(int64_t* c, int count, hipStream_t st);
+
 // dispatch over the buckets 16, 24, ..., 64
 inline int launch_group(int prec, int nb, int fam, int alg, const KArgs& a, hipStream_t st) {
 #define NLS_CASE(NB) \

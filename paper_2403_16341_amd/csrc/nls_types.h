@@ -53,6 +53,7 @@ struct KArgs {
   const int64_t* u_off;
   const int32_t* sys;
   const uint8_t* nsys;  // per-system n (group mapping, mixed sizes); may be null
+  int64_t* counter;     // dynamic work counter (zeroed before the launch); may be null
   int64_t count;
   int64_t P;
   int32_t n;            // uniform n when nsys is null
