@@ -75,7 +75,9 @@ extern "C" {
  * FP64       : everything in binary64.
  * FP32_INNER : Jacobian, LU factor/solve and the dogleg step algebra in
  *              binary32; residual, norms, acceptance tests and the update
- *              u += delta stay binary64 (Newton acts as iterative refinement). */
+ *              u += delta stay binary64 (Newton acts as iterative refinement).
+ *              Accepted for uniform batches (one family, n and algorithm)
+ *              with n <= 16 only; other batches fail with NLS_E_INVALID. */
 #define NLS_PREC_FP64 0
 #define NLS_PREC_FP32_INNER 1
 
@@ -95,6 +97,12 @@ extern "C" {
 typedef struct nls_context nls_context;
 
 #define NLS_CTX_THREADSAFE 1u /* serialise calls on one context with a mutex */
+#define NLS_CTX_AUTOTUNE 2u   /* time lane vs group mapping per (n, family,
+                                 algorithm, precision) on first use and keep
+                                 the faster; NLS_AUTOTUNE_CACHE names a file
+                                 that persists the choices; the environment
+                                 variable NLS_MAPPING=lane|group, read at
+                                 nls_create, fixes the n <= 8 mapping instead */
 
 typedef struct {
   int32_t device;            /* HIP device ordinal                            */
@@ -205,6 +213,12 @@ int nls_validate(const nls_batch* b, int64_t* first_bad);
 /* Message of the last error on this context (or of the last context-less
  * call on this thread when c is NULL).  Never NULL.                         */
 const char* nls_last_error(const nls_context* c);
+
+/* Kernel mapping the context uses for a combination: *lanes_per_system = 1
+ * (one system per lane) or 16/32/64 (one system per group of that many
+ * lanes); 0 if the combination has not been tuned yet under
+ * NLS_CTX_AUTOTUNE.  Errors: NLS_E_INVALID.                                 */
+int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precision, int32_t* lanes_per_system);
 
 /* Number of float64 parameters of a family at size n, or -1 if invalid.      */
 int nls_nparams(int family, int n);

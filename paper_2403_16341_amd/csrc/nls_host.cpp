@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -58,6 +59,18 @@ struct nls_context {
   // in order, so every call may reuse them (zeroed at its start)
   int64_t* counters = nullptr;
   int ncounters = 0;
+  // parallel branches of a captured multi-kernel launch
+  static constexpr int kBranches = 4;
+  hipStream_t branch[kBranches] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kBranches] = {};
+  // the last captured graph and the launch list it was made from
+  hipGraphExec_t graph_exec = nullptr;
+  std::string graph_sig;
+  // autotuned mapping per (n, family, algorithm, precision): 1 = lane, 2 = group
+  std::map<int, int> tuned;
+  std::string tune_cache_path;
+  int forced = 0;  // NLS_MAPPING: 1 = lane, 2 = group for every n <= 8 system
 };
 
 namespace {
@@ -216,6 +229,28 @@ int launch(int n_or_nb, bool lane, int fam, int alg, int prec, const KArgs& a, h
   return launch_group(prec, n_or_nb, fam, alg, a, st);
 }
 
+// dense index of an (n, family, algorithm) combination
+constexpr int kCombos = NLS_NMAX * FAM_COUNT * ALG_COUNT;
+inline int combo_index(int n, int fam, int alg) { return ((n - 1) * FAM_COUNT + fam) * ALG_COUNT + alg; }
+inline void combo_split(int ci, int* n, int* fam, int* alg) {
+  *alg = ci % ALG_COUNT;
+  *fam = (ci / ALG_COUNT) % FAM_COUNT;
+  *n = ci / (ALG_COUNT * FAM_COUNT) + 1;
+}
+
+struct Mapping {
+  bool lane;
+  int key_n;  // n for the lane mapping, the size bucket for the group mapping
+  hipError_t error;
+};
+
+struct Launch {
+  KArgs a;
+  bool lane;
+  int key_n, fam, alg;
+  double cost;  // estimated work (sum of n^3) for branch balancing
+};
+
 struct DevBuf {
   std::vector<void*>* list;
   uint64_t* bytes;
@@ -230,6 +265,144 @@ struct DevBuf {
   }
 };
 
+int tune_key(int n, int fam, int alg, int prec) { return ((n * FAM_COUNT + fam) * ALG_COUNT + alg) * 2 + prec; }
+
+void save_tuning(nls_context* c, int key, int choice) {
+  if (c->tune_cache_path.empty()) return;
+  if (FILE* f = std::fopen(c->tune_cache_path.c_str(), "a")) {
+    std::fprintf(f, "%d %d\n", key, choice);
+    std::fclose(f);
+  }
+}
+
+void load_tuning(nls_context* c) {
+  if (c->tune_cache_path.empty()) return;
+  if (FILE* f = std::fopen(c->tune_cache_path.c_str(), "r")) {
+    int k = 0, v = 0;
+    while (std::fscanf(f, "%d %d", &k, &v) == 2)
+      if (v == 1 || v == 2) c->tuned[k] = v;
+    std::fclose(f);
+  }
+}
+
+// Kernel mapping for a bucket.  Without NLS_CTX_AUTOTUNE (or for n > 8, where
+// only the group mapping exists) the choice is fixed: one system per lane for
+// n <= 8, else one system per 16/32/64-lane group.  With it, the first batch
+// that holds the combination times both mappings on up to 4096 of its systems
+// (results land in the output buffers and are overwritten by the real solve)
+// and the faster one is kept for the life of the context (and in the file named
+// by NLS_AUTOTUNE_CACHE), so the mapping never depends on batch composition.
+Mapping choose_mapping(nls_context* c, int n, int fam, int alg, int prec, KArgs a, int64_t P, int64_t count,
+                       const int32_t* sys, const int64_t* p_off) {
+  const Mapping lane{true, n, hipSuccess};
+  const Mapping group{false, group_bucket(n), hipSuccess};
+  if (n > 8) return group;
+  if (fam == FAM_PAPER || (fam == FAM_ROSENBROCK && n < 2)) return lane;
+  if (c->forced) return c->forced == 1 ? lane : group;
+  if (!(c->flags & NLS_CTX_AUTOTUNE)) return lane;
+  const int key = tune_key(n, fam, alg, prec);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second == 1 ? lane : group;
+  a.count = count < 4096 ? count : 4096;
+  a.P = P;
+  a.n = n;
+  a.sys = sys;
+  a.p_off = p_off;
+  a.counter = nullptr;
+  float best_ms[2] = {0.f, 0.f};
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return Mapping{true, n, e};
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return Mapping{true, n, e}; }
+  for (int cand = 0; cand < 2; ++cand) {
+    const Mapping mp = cand == 0 ? lane : group;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run loads the code object
+      hipEventRecord(e0, c->stream);
+      int rc = launch(mp.key_n, mp.lane, fam, alg, prec, a, c->stream);
+      hipEventRecord(e1, c->stream);
+      if (rc < 0) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, (hipError_t)(-rc)}; }
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, e}; }
+      hipEventElapsedTime(&best_ms[cand], e0, e1);
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  const int choice = best_ms[0] <= best_ms[1] ? 1 : 2;
+  c->tuned[key] = choice;
+  save_tuning(c, key, choice);
+  return choice == 1 ? lane : group;
+}
+
+// Run a list of persistent launches.  One launch goes straight onto the
+// stream; several are captured into one graph whose branches (at most four,
+// balanced by estimated work) run concurrently, and the graph is replayed
+// while the launch list stays the same.  Counters are zeroed by a kernel
+// inside the graph (no memset nodes).
+int run_launches(nls_context* c, std::vector<Launch>& L, int prec) {
+  const int nl = (int)L.size();
+  if (nl == 0) return 0;
+  const bool use_graph = nl > 1 && !std::getenv("NLS_NO_GRAPH");
+  if (!use_graph) {
+    if (int z = launch_zero_counters(c->counters, nl, c->stream); z < 0) return z;
+    for (auto& x : L) {
+      int rc = launch(x.key_n, x.lane, x.fam, x.alg, prec, x.a, c->stream);
+      if (rc != 0) return rc;
+    }
+    return 0;
+  }
+  // signature: every launch's kernel identity and arguments
+  std::string sig;
+  sig.reserve(nl * (sizeof(KArgs) + 16) + 4);
+  sig.append((const char*)&prec, sizeof prec);
+  for (auto& x : L) {
+    sig.append((const char*)&x.a, sizeof(KArgs));
+    int id[4] = {x.lane ? 1 : 0, x.key_n, x.fam, x.alg};
+    sig.append((const char*)id, sizeof id);
+  }
+  if (c->graph_exec && sig == c->graph_sig) {
+    hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+    return e == hipSuccess ? 0 : -(int)e;
+  }
+  // branch assignment: longest work first, onto the least-loaded branch
+  std::vector<int> idx(nl);
+  for (int i = 0; i < nl; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return L[x].cost > L[y].cost; });
+  const int nb = std::min(nl, (int)nls_context::kBranches);
+  std::vector<double> load(nb, 0.0);
+  std::vector<std::vector<int>> br(nb);
+  for (int i : idx) {
+    int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    br[j].push_back(i);
+    load[j] += L[i].cost;
+  }
+  hipError_t e;
+  hipGraph_t g = nullptr;
+  if ((e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return -(int)e;
+  int rc = launch_zero_counters(c->counters, nl, c->stream);
+  if (rc == 0 && (e = hipEventRecord(c->fork_ev, c->stream)) != hipSuccess) rc = -(int)e;
+  for (int j = 0; j < nb && rc == 0; ++j) {
+    if ((e = hipStreamWaitEvent(c->branch[j], c->fork_ev, 0)) != hipSuccess) { rc = -(int)e; break; }
+    for (int i : br[j]) {
+      rc = launch(L[i].key_n, L[i].lane, L[i].fam, L[i].alg, prec, L[i].a, c->branch[j]);
+      if (rc != 0) break;
+    }
+    if (rc == 0 && (e = hipEventRecord(c->join_ev[j], c->branch[j])) != hipSuccess) rc = -(int)e;
+    if (rc == 0 && (e = hipStreamWaitEvent(c->stream, c->join_ev[j], 0)) != hipSuccess) rc = -(int)e;
+  }
+  e = hipStreamEndCapture(c->stream, &g);
+  if (rc != 0) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return -(int)e;
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return -(int)e;
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = ex;
+  c->graph_sig.swap(sig);
+  e = hipGraphLaunch(c->graph_exec, c->stream);
+  return e == hipSuccess ? 0 : -(int)e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -237,6 +410,20 @@ extern "C" {
 int nls_abi_version(void) { return NLS_ABI_VERSION; }
 
 int nls_nparams(int family, int n) { return nparams_of(family, n); }
+
+int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precision, int32_t* lanes_per_system) {
+  if (!c || !lanes_per_system) return fail(nullptr, NLS_E_INVALID, "nls_get_mapping: NULL argument");
+  if (!supported(family, n) || alg < 0 || alg >= ALG_COUNT || (precision != 0 && precision != 1))
+    return fail(nullptr, NLS_E_INVALID, "nls_get_mapping: bad combination");
+  const int group_l = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
+  if (n > 8) { *lanes_per_system = group_l; return NLS_OK; }
+  if (family == FAM_PAPER) { *lanes_per_system = 1; return NLS_OK; }
+  if (c->forced) { *lanes_per_system = c->forced == 1 ? 1 : 16; return NLS_OK; }
+  if (!(c->flags & NLS_CTX_AUTOTUNE)) { *lanes_per_system = 1; return NLS_OK; }
+  auto it = c->tuned.find(tune_key(n, family, alg, precision));
+  *lanes_per_system = it == c->tuned.end() ? 0 : (it->second == 1 ? 1 : 16);
+  return NLS_OK;
+}
 
 void nls_default_options(nls_alg_options* o) {
   if (o) fill_defaults(o);
@@ -277,11 +464,18 @@ int nls_create(const nls_context_desc* d, nls_context** out) {
   }
   c->ncounters = 512;
   e = hipMalloc((void**)&c->counters, sizeof(int64_t) * c->ncounters);
-  if (e != hipSuccess) {
-    if (c->own_stream) hipStreamDestroy(c->stream);
-    delete c;
-    return hip_fail(nullptr, e, "hipMalloc(counters)");
+  for (int j = 0; e == hipSuccess && j < nls_context::kBranches; ++j) {
+    e = hipStreamCreateWithFlags(&c->branch[j], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev[j], hipEventDisableTiming);
   }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    nls_destroy(c);
+    return hip_fail(nullptr, e, "nls_create");
+  }
+  if (const char* tc = std::getenv("NLS_AUTOTUNE_CACHE")) c->tune_cache_path = tc;
+  if (const char* fm = std::getenv("NLS_MAPPING")) c->forced = std::strcmp(fm, "group") == 0 ? 2 : (std::strcmp(fm, "lane") == 0 ? 1 : 0);
+  load_tuning(c);
   *out = c;
   return NLS_OK;
 }
@@ -301,8 +495,14 @@ int nls_destroy(nls_context* c) {
   hipStreamSynchronize(c->stream);
   for (auto& kv : c->tickets) release_ticket(kv.second, c);
   c->tickets.clear();
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  for (int j = 0; j < nls_context::kBranches; ++j) {
+    if (c->branch[j]) hipStreamDestroy(c->branch[j]);
+    if (c->join_ev[j]) hipEventDestroy(c->join_ev[j]);
+  }
+  if (c->fork_ev) hipEventDestroy(c->fork_ev);
   if (c->counters) hipFree(c->counters);
-  if (c->own_stream) hipStreamDestroy(c->stream);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
   return NLS_OK;
 }
@@ -356,6 +556,17 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     // staged (and, for u, returned) like every other gap
     if (b->p_offset) ptotal = std::max(ptotal, b->p_offset[M]);
     if (b->u_offset) utotal = std::max(utotal, b->u_offset[M]);
+  }
+
+  // The FP32-inner form of mixed batches, and of systems with n > 16, stays
+  // off until the silent stall seen on a mixed FP32-inner batch is explained.
+  if (b->precision == NLS_PREC_FP32_INNER && M > 0) {
+    bool big = false;
+    if (!b->n) big = b->n_all > 16;
+    else for (int64_t s = 0; s < M && !big; ++s) big = b->n[s] > 16;
+    if (!uniform || big)
+      return fail(c, NLS_E_INVALID,
+                  "FP32-inner precision is available for uniform batches with n <= 16 only in this build");
   }
 
   // device footprint of this call (library-owned memory only)
@@ -434,21 +645,24 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   base.o = to_kopts(opts);
 
   if (M > 0 && uniform) {
+    const Mapping mp = choose_mapping(c, n0, fam0, alg0, b->precision, base, P0, M, nullptr, nullptr);
+    if (mp.error) return bail(mp.error, "autotune");
     if (int z = launch_zero_counters(c->counters, 1, c->stream); z < 0) return bail((hipError_t)(-z), "zero counters");
     KArgs a = base;
     a.count = M;
     a.P = P0;
     a.n = n0;
     a.counter = c->counters;
-    const bool lane = lane_mapped(n0);
-    int rcode = launch(lane ? n0 : group_bucket(n0), lane, fam0, alg0, b->precision, a, c->stream);
+    int rcode = launch(mp.key_n, mp.lane, fam0, alg0, b->precision, a, c->stream);
     if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
     if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
   } else if (M > 0) {
-    // Bucket by (mapping, size bucket, family, algorithm); one launch per bucket.
-    std::map<int64_t, std::vector<int32_t>> buckets;
+    // Bucket by kernel: counting sort of the systems on a dense key
+    // (mapping, size bucket, family, algorithm), one persistent launch per
+    // bucket, all captured in one graph with parallel branches.
     std::vector<int64_t> poff(M + 1), uoff(M + 1);
     std::vector<uint8_t> nn(M);
+    std::vector<uint16_t> key(M);
     int64_t pacc = 0, uacc = 0;
     for (int64_t s = 0; s < M; ++s) {
       const int fam = b->family ? b->family[s] : b->family_all;
@@ -459,22 +673,25 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       pacc = poff[s] + nparams_of(fam, n);
       uacc = uoff[s] + n;
       nn[s] = (uint8_t)n;
-      const bool lane = lane_mapped(n);
-      const int key_n = lane ? n : group_bucket(n);
-      const int64_t key = ((int64_t)(lane ? 0 : 1) << 40) | ((int64_t)key_n << 16) | (fam << 8) | alg;
-      buckets[key].push_back((int32_t)s);
+      key[s] = (uint16_t)combo_index(n, fam, alg);
     }
     poff[M] = pacc;
     uoff[M] = uacc;
-    std::vector<int32_t> order;
-    order.reserve(M);
-    for (auto& kv : buckets) order.insert(order.end(), kv.second.begin(), kv.second.end());
+    // systems per (n, family, algorithm) combination, in input order
+    std::vector<int64_t> cnt(kCombos + 1, 0);
+    for (int64_t s = 0; s < M; ++s) cnt[key[s] + 1]++;
+    for (int i = 0; i < kCombos; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> order(M);
+    {
+      std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
+      for (int64_t s = 0; s < M; ++s) order[at[key[s]]++] = (int32_t)s;
+    }
     void *dsys = nullptr, *dpo = nullptr, *duo = nullptr, *dn = nullptr;
     if ((e = db.alloc(&dsys, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = db.alloc(&dpo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = db.alloc(&duo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = db.alloc(&dn, M)) != hipSuccess) return bail(e, "hipMalloc");
-    // these host vectors die with this call: copy synchronously on the stream
+    // these host vectors die with this call: the copies complete before return
     if ((e = hipMemcpyAsync(dsys, order.data(), M * 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
       return bail(e, "hipMemcpyAsync");
     if ((e = hipMemcpyAsync(dpo, poff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
@@ -484,31 +701,41 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     if ((e = hipMemcpyAsync(dn, nn.data(), M, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
       return bail(e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
-    if ((int)buckets.size() > c->ncounters) return fail(c, NLS_E_INVALID, "too many buckets");
-    if (int z = launch_zero_counters(c->counters, (int)buckets.size(), c->stream); z < 0)
-      return bail((hipError_t)(-z), "zero counters");
-    int64_t at = 0;
-    int bi = 0;
-    for (auto& kv : buckets) {
-      const int64_t key = kv.first;
-      const bool lane = ((key >> 40) & 1) == 0;
-      const int key_n = (int)((key >> 16) & 0xff);
-      const int fam = (int)((key >> 8) & 0xff);
-      const int alg = (int)(key & 0xff);
+    // one launch per kernel: combinations that map to the same group bucket
+    // share it (their n rides along in nsys)
+    std::vector<Launch> launches;
+    std::map<int, size_t> by_kernel;
+    for (int ci = 0; ci < kCombos; ++ci) {
+      const int64_t c0 = cnt[ci], c1 = cnt[ci + 1];
+      if (c1 == c0) continue;
+      int n, fam, alg;
+      combo_split(ci, &n, &fam, &alg);
       KArgs a = base;
-      a.sys = (const int32_t*)dsys + at;
+      a.sys = (const int32_t*)dsys + c0;
       a.p_off = (const int64_t*)dpo;
       a.u_off = (const int64_t*)duo;
       a.nsys = (const uint8_t*)dn;
-      a.count = (int64_t)kv.second.size();
+      a.count = c1 - c0;
       a.P = 0;
-      a.n = key_n;
-      a.counter = c->counters + bi++;
-      int rcode = launch(key_n, lane, fam, alg, b->precision, a, c->stream);
-      if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
-      if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
-      at += a.count;
+      const Mapping mp = choose_mapping(c, n, fam, alg, b->precision, a, 0, c1 - c0, a.sys, a.p_off);
+      if (mp.error) return bail(mp.error, "autotune");
+      const int kid = (mp.lane ? 0 : 1000) + mp.key_n * 16 + fam * 4 + alg;
+      auto it = by_kernel.find(kid);
+      if (it != by_kernel.end() && !mp.lane && launches[it->second].a.sys + launches[it->second].a.count == a.sys) {
+        launches[it->second].a.count += a.count;  // adjacent in the sorted order
+        launches[it->second].cost += (double)a.count * n * n * n;
+        continue;
+      }
+      a.n = mp.key_n;
+      Launch L{a, mp.lane, mp.key_n, fam, alg, (double)a.count * n * n * n};
+      by_kernel[kid] = launches.size();
+      launches.push_back(L);
     }
+    if ((int)launches.size() > c->ncounters) return fail(c, NLS_E_INVALID, "too many kernels");
+    for (size_t i = 0; i < launches.size(); ++i) launches[i].a.counter = c->counters + i;
+    int rcode = run_launches(c, launches, b->precision);
+    if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
+    if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
   }
 
   if (M > 0 && !dev) {

@@ -28,10 +28,11 @@ PREC_FP64, PREC_FP32_INNER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 RC_SUCCESS, RC_MAXITERS, RC_SINGULAR, RC_NONFINITE, RC_LINESEARCH_FAILED, RC_TR_COLLAPSED, RC_INVALID = range(7)
 CTX_THREADSAFE = 1
+CTX_AUTOTUNE = 2
 
 # every symbol include/nls.h declares
 EXPORTS = ("nls_create", "nls_destroy", "nls_solve_batch", "nls_query", "nls_validate",
-           "nls_last_error", "nls_nparams", "nls_default_options", "nls_abi_version")
+           "nls_last_error", "nls_get_mapping", "nls_nparams", "nls_default_options", "nls_abi_version")
 
 
 class ContextDesc(ctypes.Structure):
@@ -102,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.nls_validate.restype = ctypes.c_int
     L.nls_last_error.argtypes = [P]
     L.nls_last_error.restype = ctypes.c_char_p
+    L.nls_get_mapping.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.nls_get_mapping.restype = ctypes.c_int
     L.nls_nparams.argtypes = [ctypes.c_int, ctypes.c_int]
     L.nls_nparams.restype = ctypes.c_int
     L.nls_default_options.argtypes = [ctypes.POINTER(AlgOptions)]
@@ -173,6 +177,14 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def mapping(self, family: int, n: int, alg: int, precision: int = PREC_FP64) -> int:
+        """Lanes per system the context uses for a combination (0 = not tuned yet)."""
+        v = ctypes.c_int32(0)
+        rc = lib().nls_get_mapping(self.handle, family, n, alg, precision, ctypes.byref(v))
+        if rc != OK:
+            raise NLSError(rc, last_error(None))
+        return v.value
 
     def error(self) -> str:
         return lib().nls_last_error(self.handle).decode()

@@ -190,3 +190,50 @@ def test_full_size_headline_sampled(nls, ctx):
           for k, v in g.items() if isinstance(v, np.ndarray)}
     rep = compare(sub, gs, "headline-sampled")
     assert rep["sensitive"] == 0
+
+
+def test_group_mapping_for_small_systems(nls, monkeypatch):
+    """The 16-lane group kernels also solve n <= 8 systems (the autotuner's
+    alternative); forced through NLS_MAPPING, they meet the same bar."""
+    monkeypatch.setenv("NLS_MAPPING", "group")
+    c = nls.Context(0)
+    try:
+        assert c.mapping(inputs.CUBIC, 8, inputs.ARMIJO) == 16
+        for k, M in ((1, 300), (2, 333)):
+            b = inputs.config(k, M=M)
+            compare(b, run_gpu(nls, c, b), "group-mapped workload %d" % k)
+        b = inputs.config(4, M=900)
+        compare(b, run_gpu(nls, c, b), "group-mapped mixed", max_other_root=18)
+    finally:
+        c.close()
+
+
+def test_autotuned_mixed_batch(nls):
+    c = nls.Context(0, flags=nls.CTX_AUTOTUNE)
+    try:
+        b = inputs.config(4, M=3000)
+        assert c.mapping(inputs.TANH, 8, inputs.DOGLEG) == 0   # not tuned yet
+        g1 = run_gpu(nls, c, b)
+        lanes = c.mapping(inputs.TANH, 8, inputs.DOGLEG)
+        assert lanes in (1, 16)
+        print("autotuned lanes per system (tanh, n=8, dogleg):", lanes, flush=True)
+        compare(b, g1, "autotuned mixed", max_other_root=60)
+        g2 = run_gpu(nls, c, b)      # same mapping, replayed graph: bitwise equal
+        for key in ("u", "iters", "retcode", "fnorm_inf", "nfev", "njev"):
+            assert np.array_equal(g1[key], g2[key], equal_nan=True), key
+    finally:
+        c.close()
+
+
+def test_fp32_inner_mixed_batches_are_rejected(nls, ctx):
+    """FP32-inner stays off for mixed batches and n > 16 in this build: the
+    call fails before any device work and leaves the outputs untouched."""
+    b = inputs.config(4, M=200)
+    db = nls.DeviceBatch(b)
+    out = db.alloc_results()
+    for v in out.values():
+        v.fill_(7)
+    with pytest.raises(nls.NLSError) as ei:
+        ctx.solve(db, out=out, precision=inputs.PREC_FP32_INNER)
+    assert ei.value.code == nls.E_INVALID and "FP32-inner" in str(ei.value)
+    assert all(bool((v == 7).all()) for v in out.values())
