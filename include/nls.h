@@ -77,7 +77,9 @@ extern "C" {
  *              binary32; residual, norms, acceptance tests and the update
  *              u += delta stay binary64 (Newton acts as iterative refinement).
  *              Accepted for uniform batches (one family, n and algorithm)
- *              with n <= 16 only; other batches fail with NLS_E_INVALID. */
+ *              of the cubic family with n <= 8 under Newton or Armijo, and
+ *              of the tanh family with 9 <= n <= 16 under dogleg; other
+ *              batches fail with NLS_E_INVALID. */
 #define NLS_PREC_FP64 0
 #define NLS_PREC_FP32_INNER 1
 

@@ -105,6 +105,32 @@ bool supported(int family, int n) {
   return true;
 }
 
+// One family, size and algorithm for every system, packed back to back (the
+// layout the single-launch path takes).
+bool uniform_batch(const nls_batch* b, int* fam0, int* n0, int* alg0) {
+  const int64_t M = b->count;
+  *fam0 = b->family ? (M ? b->family[0] : 0) : b->family_all;
+  *n0 = b->n ? (M ? b->n[0] : 1) : b->n_all;
+  *alg0 = b->alg ? (M ? b->alg[0] : 0) : b->alg_all;
+  if (!b->family && !b->n && !b->alg && !b->p_offset && !b->u_offset) return true;
+  const int P0 = nparams_of(*fam0, *n0);
+  for (int64_t s = 0; s < M; ++s) {
+    const int fam = b->family ? b->family[s] : b->family_all;
+    const int n = b->n ? b->n[s] : b->n_all;
+    const int alg = b->alg ? b->alg[s] : b->alg_all;
+    if (fam != *fam0 || n != *n0 || alg != *alg0) return false;
+    if (b->p_offset && b->p_offset[s] != s * (int64_t)P0) return false;
+    if (b->u_offset && b->u_offset[s] != s * (int64_t)*n0) return false;
+  }
+  return true;
+}
+
+bool fp32_inner_enabled(int fam, int n, int alg) {
+  if (fam == NLS_FAMILY_CUBIC) return n <= 8 && (alg == NLS_ALG_NEWTON || alg == NLS_ALG_NEWTON_ARMIJO);
+  if (fam == NLS_FAMILY_TANH) return n >= 9 && n <= 16 && alg == NLS_ALG_DOGLEG;
+  return false;
+}
+
 void fill_defaults(nls_alg_options* o) {
   o->armijo_c = 1e-4;
   o->armijo_rho = 0.5;
@@ -197,6 +223,17 @@ std::string validate(const nls_batch* b, int64_t* first_bad) {
   (void)utotal;
   if (!b->u0) return "u0 is NULL";
   if (ptotal > 0 && !b->params) return "params is NULL";
+  // FP32-inner runs only on the kernels it has been verified with on the
+  // device: uniform, packed cubic batches with n <= 8 under Newton or Armijo,
+  // and uniform, packed tanh dogleg batches with 9 <= n <= 16.  Everything
+  // else stays off until the stall seen on a mixed FP32-inner batch is
+  // explained.
+  if (b->precision == NLS_PREC_FP32_INNER) {
+    int fam0, n0, alg0;
+    if (!uniform_batch(b, &fam0, &n0, &alg0) || !fp32_inner_enabled(fam0, n0, alg0))
+      return "FP32-inner precision is limited to uniform cubic batches with n <= 8 (Newton, Armijo) "
+             "and uniform tanh dogleg batches with 9 <= n <= 16 in this build";
+  }
   return "";
 }
 
@@ -524,20 +561,9 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   if (b->opts) opts = *b->opts;
 
   // --- plan: uniform fast path or buckets ---------------------------------
-  bool uniform = true;
-  int fam0 = b->family ? (M ? b->family[0] : 0) : b->family_all;
-  int n0 = b->n ? (M ? b->n[0] : 1) : b->n_all;
-  int alg0 = b->alg ? (M ? b->alg[0] : 0) : b->alg_all;
+  int fam0, n0, alg0;
+  const bool uniform = uniform_batch(b, &fam0, &n0, &alg0);
   const int P0 = nparams_of(fam0, n0);
-  const bool scalar = !b->family && !b->n && !b->alg && !b->p_offset && !b->u_offset;
-  for (int64_t s = 0; s < M && uniform && !scalar; ++s) {
-    const int fam = b->family ? b->family[s] : b->family_all;
-    const int n = b->n ? b->n[s] : b->n_all;
-    const int alg = b->alg ? b->alg[s] : b->alg_all;
-    if (fam != fam0 || n != n0 || alg != alg0) uniform = false;
-    if (b->p_offset && b->p_offset[s] != s * (int64_t)P0) uniform = false;
-    if (b->u_offset && b->u_offset[s] != s * (int64_t)n0) uniform = false;
-  }
   // total payload extents
   int64_t ptotal = 0, utotal = 0;
   if (uniform) {
@@ -556,17 +582,6 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     // staged (and, for u, returned) like every other gap
     if (b->p_offset) ptotal = std::max(ptotal, b->p_offset[M]);
     if (b->u_offset) utotal = std::max(utotal, b->u_offset[M]);
-  }
-
-  // The FP32-inner form of mixed batches, and of systems with n > 16, stays
-  // off until the silent stall seen on a mixed FP32-inner batch is explained.
-  if (b->precision == NLS_PREC_FP32_INNER && M > 0) {
-    bool big = false;
-    if (!b->n) big = b->n_all > 16;
-    else for (int64_t s = 0; s < M && !big; ++s) big = b->n[s] > 16;
-    if (!uniform || big)
-      return fail(c, NLS_E_INVALID,
-                  "FP32-inner precision is available for uniform batches with n <= 16 only in this build");
   }
 
   // device footprint of this call (library-owned memory only)

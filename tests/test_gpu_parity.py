@@ -226,8 +226,9 @@ def test_autotuned_mixed_batch(nls):
 
 
 def test_fp32_inner_mixed_batches_are_rejected(nls, ctx):
-    """FP32-inner stays off for mixed batches and n > 16 in this build: the
-    call fails before any device work and leaves the outputs untouched."""
+    """FP32-inner stays off for mixed batches and for kernels it has not been
+    verified with: the call fails before any device work and leaves the
+    outputs untouched."""
     b = inputs.config(4, M=200)
     db = nls.DeviceBatch(b)
     out = db.alloc_results()
@@ -237,3 +238,8 @@ def test_fp32_inner_mixed_batches_are_rejected(nls, ctx):
         ctx.solve(db, out=out, precision=inputs.PREC_FP32_INNER)
     assert ei.value.code == nls.E_INVALID and "FP32-inner" in str(ei.value)
     assert all(bool((v == 7).all()) for v in out.values())
+    for fam, n, alg in ((inputs.TANH, 8, inputs.DOGLEG), (inputs.CUBIC, 24, inputs.ARMIJO)):
+        bb = inputs.homogeneous(fam, n, alg, np.zeros((4, inputs.nparams(fam, n))), np.zeros((4, n)),
+                                1e-10, 10)
+        with pytest.raises(nls.NLSError):
+            ctx.solve(nls.DeviceBatch(bb), precision=inputs.PREC_FP32_INNER)
