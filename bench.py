@@ -154,6 +154,91 @@ def extra_workloads(nls, ctx, args):
     return out
 
 
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
+
+
+def serving_leg(nls, args):
+    """Request server under load: Poisson arrivals of requests of 1..65,536
+    systems (log-uniform) with n ~ U{2..64}, cubic/Armijo or tanh/dogleg 50/50.
+    First a closed-loop pass (every request queued at once) measures capacity;
+    then open-loop streams at fractions of that capacity report p50/p99
+    latency (submit to results in the caller's arrays) and solves/s.  Every
+    request's results are checked bitwise against its closed-loop results
+    (the same request alone in the queue vs in the mix)."""
+    from paper_2403_16341_amd import inputs
+    t0 = time.perf_counter()
+    pool = inputs.serving_requests(args.serve_payloads, rate_hz=1.0, precision=inputs.PREC_FP64)
+    print("[bench] serving: %d request payloads generated (%.1f s), %d systems"
+          % (len(pool), time.perf_counter() - t0, sum(r.batch.M for r in pool)), file=sys.stderr, flush=True)
+    srv = nls.Server(0, mem_budget_bytes=args.serve_budget_gib << 30, streams=4)
+    keys = ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev")
+
+    # closed loop: capacity, and the per-payload reference results
+    t0 = time.perf_counter()
+    ids = {srv.submit(r.batch): j for j, r in enumerate(pool)}
+    done = srv.drain()
+    wall = time.perf_counter() - t0
+    ref = {}
+    conv = 0
+    for info, out in done:
+        ref[ids[info["id"]]] = out
+        conv += int((out["retcode"] == 0).sum())
+    cap_rps = len(pool) / wall
+    res = {"payloads": len(pool), "systems": int(sum(r.batch.M for r in pool)),
+           "budget_bytes": srv.stats()["budget_bytes"], "streams": 4,
+           "closed_loop": {"wall_s": wall, "requests_per_s": cap_rps, "converged": conv,
+                           "solves_per_s": conv / wall}}
+    print("[bench] serving closed loop: %.2f s, %.2f req/s, %.0f solves/s"
+          % (wall, cap_rps, conv / wall), file=sys.stderr, flush=True)
+
+    rng = np.random.Generator(np.random.PCG64(20240316 * 7))
+    same = True
+    res["open_loop"] = []
+    for frac in args.serve_load:
+        rate = frac * cap_rps
+        R = args.serve_stream
+        order = rng.integers(0, len(pool), size=R)
+        arrive = np.cumsum(rng.exponential(1.0 / rate, size=R))
+        t_start = time.perf_counter()
+        which, infos = {}, []
+        for j in range(R):
+            while True:
+                dt = arrive[j] - (time.perf_counter() - t_start)
+                if dt <= 0:
+                    break
+                for info, out in srv.poll(wait_ms=max(0, min(int(dt * 1e3), 5))):
+                    infos.append((info, out))
+            which[srv.submit(pool[order[j]].batch)] = int(order[j])
+        infos += srv.drain()
+        wall = time.perf_counter() - t_start
+        lat = [i["t_done_ms"] - i["t_submit_ms"] for i, _ in infos]
+        queue = [i["t_admit_ms"] - i["t_submit_ms"] for i, _ in infos]
+        conv = 0
+        for info, out in infos:
+            conv += int((out["retcode"] == 0).sum())
+            r = ref[which[info["id"]]]
+            same = same and all(np.array_equal(out[k], r[k]) for k in keys)
+        sizes = np.array([i["systems"] for i, _ in infos])
+        lat = np.array(lat)
+        small = lat[sizes <= 256]
+        e = {"load": frac, "rate_hz": rate, "requests": R, "wall_s": wall,
+             "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": float(lat.max()),
+             "p50_small_ms": _pct(small, 50), "p99_small_ms": _pct(small, 99),
+             "p50_queue_ms": _pct(queue, 50), "p99_queue_ms": _pct(queue, 99),
+             "mean_merged": float(np.mean([i["merged"] for i, _ in infos])),
+             "converged": conv, "solves_per_s": conv / wall}
+        res["open_loop"].append(e)
+        print("[bench] serving at %.2f x capacity (%.2f req/s): p50 %.1f ms, p99 %.1f ms, %.0f solves/s"
+              % (frac, rate, e["p50_ms"], e["p99_ms"], e["solves_per_s"]), file=sys.stderr, flush=True)
+    st = srv.stats()
+    res["peak_resident_bytes"] = st["peak_resident_bytes"]
+    res["launches"] = st["launches"]
+    res["alone_vs_mix_bitwise_equal"] = bool(same)
+    srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +247,12 @@ def main():
     ap.add_argument("--systems", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the tanh N=16 and mixed workloads")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--serve-payloads", type=int, default=64, help="distinct request payloads")
+    ap.add_argument("--serve-stream", type=int, default=256, help="requests per open-loop stream")
+    ap.add_argument("--serve-load", type=lambda x: [float(v) for v in x.split(",")], default=[0.5, 0.8],
+                    help="open-loop arrival rates as fractions of the closed-loop capacity")
+    ap.add_argument("--serve-budget-gib", type=int, default=8, help="server device-memory budget")
     ap.add_argument("--forms", default="fp64,fp32", help="precision forms to time (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
@@ -259,6 +350,9 @@ def main():
 
     if not args.no_extra:
         res["workloads"] = extra_workloads(nls, ctx, args)
+
+    if not args.no_serving:
+        res["serving"] = serving_leg(nls, args)
 
     if not args.no_cpu_baseline:
         import oracle

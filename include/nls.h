@@ -30,7 +30,8 @@
  *     GPU, e.g. torch tensors' data_ptr()).
  *   - the library never retains a pointer to caller memory beyond the call,
  *     except device payload pointers, which it reads/writes until nls_query
- *     reports the ticket done.
+ *     reports the ticket done, and the arrays of a server request (see the
+ *     request server below), held until nls_server_poll reports it.
  */
 #ifndef NLS_H
 #define NLS_H
@@ -230,6 +231,79 @@ void nls_default_options(nls_alg_options* o);
 
 /* NLS_ABI_VERSION of the loaded library.                                     */
 int nls_abi_version(void);
+
+/* ---- request server ------------------------------------------------------
+ * Continuous batching of independent solve requests that arrive over time
+ * (the many-independent-solves setting of Sec. 4, served as a stream).  A
+ * scheduler thread owned by the server admits queued requests first come,
+ * first served into a device arena of mem_budget_bytes (with a pinned host
+ * mirror of the same size for the copies); requests admitted together that
+ * share a kernel, tolerance, iteration cap and options run as one persistent
+ * launch; launches go to the least-loaded of `streams` streams, so work
+ * admitted while other work runs overlaps with it on the device.  A request
+ * whose footprint does not fit waits (it blocks the requests behind it) until
+ * completed requests release memory.  A system's result depends only on its
+ * own inputs: it is the same whether its request ran alone or in a mix.
+ *
+ * Requests are host-memory batches (mem_kind = NLS_MEM_HOST) of one family,
+ * size and algorithm.  The server reads the batch's arrays (params, u0,
+ * p_offset, u_offset) when it admits the request and writes the result
+ * arrays when the request completes: unlike nls_solve_batch, the caller keeps
+ * every array of a submitted request alive and untouched until nls_server_poll
+ * has reported the request.                                                  */
+typedef struct nls_server nls_server;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                            */
+  int32_t streams;           /* concurrent streams, 1..16 (0 = 4)             */
+  uint64_t mem_budget_bytes; /* device arena for admitted requests (> 0)      */
+  int32_t max_inflight;      /* launches in flight at once, 1..4096 (0 = 256)  */
+  int32_t max_admit;         /* requests admitted per scheduling step (0 = 256) */
+} nls_server_desc;
+
+typedef struct {
+  uint64_t id;           /* as returned by nls_server_submit                   */
+  int32_t status;        /* NLS_OK, or NLS_E_DEVICE if its launch failed       */
+  int32_t merged;        /* requests that shared its launch (1 = alone)        */
+  int64_t systems;       /* M                                                  */
+  double t_submit_ms;    /* host clock stamps, ms since the server was created */
+  double t_admit_ms;     /*   admitted: taken from the queue by a scheduling   */
+                         /*   step (every request of a step has its stamp)     */
+  double t_done_ms;      /*   results written to the caller's arrays           */
+} nls_request_info;
+
+typedef struct {
+  int64_t queued;            /* submitted, not yet admitted                   */
+  int64_t inflight_launches; /* launches enqueued, not yet complete           */
+  int64_t completed;         /* requests reported or ready to report          */
+  int64_t launches;          /* launches issued since creation                */
+  uint64_t resident_bytes;   /* arena bytes held by admitted requests         */
+  uint64_t peak_resident_bytes;
+  uint64_t budget_bytes;     /* arena capacity (mem_budget_bytes, rounded)    */
+} nls_server_stats;
+
+/* Create a server: allocates the device arena and its pinned host mirror and
+ * starts the scheduler thread.  Errors: NLS_E_INVALID (NULL, bad device or
+ * field), NLS_E_NOMEM / NLS_E_DEVICE (allocation failed).                   */
+int nls_server_create(const nls_server_desc* d, nls_server** out);
+
+/* Queue one request (validated as by nls_validate, plus the rules above).
+ * r: host result arrays (nfev/njev may be NULL).  *id receives its id.
+ * Errors: NLS_E_INVALID, NLS_E_NOMEM (its footprint exceeds the arena).     */
+int nls_server_submit(nls_server* s, const nls_batch* b, const nls_results* r, uint64_t* id);
+
+/* Report completed requests: waits up to wait_ms (0 = poll, < 0 = until at
+ * least one is ready or nothing is outstanding), then moves up to max_out
+ * completed requests, oldest completion first, into out and sets *n_out.
+ * A reported request is forgotten by the server.  Errors: NLS_E_INVALID.    */
+int nls_server_poll(nls_server* s, int32_t wait_ms, nls_request_info* out, int32_t max_out, int32_t* n_out);
+
+/* Counters of the server (a consistent snapshot).                           */
+int nls_server_stats_get(nls_server* s, nls_server_stats* st);
+
+/* Drain (every submitted request runs to completion and its results are
+ * written), stop the scheduler and free everything.  NULL is a no-op.       */
+int nls_server_destroy(nls_server* s);
 
 #ifdef __cplusplus
 }

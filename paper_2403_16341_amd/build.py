@@ -24,7 +24,8 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE,
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-# device code: no packed FP32 instructions (hardware notes)
+# device code: no packed FP32 instructions (some of their forms have given
+# wrong results on gfx950 without any error); FMA contraction allowed
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast"]
 
@@ -32,6 +33,7 @@ GROUP_BUCKETS = (16, 24, 32, 40, 48, 56, 64)
 SOURCES = [
     # (file, is_device)
     ("nls_host.cpp", False),
+    ("nls_serve.cpp", False),
     ("nls_util.hip", True),
     ("nls_lane_f64.hip", True),
     ("nls_lane_f32.hip", True),
@@ -70,7 +72,7 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
                 print("[nls build] compiled", futs[f], flush=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *sorted(objs),
-           "-Wl,--no-undefined", "-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
+           "-Wl,--no-undefined", "-pthread", "-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), res.stdout, res.stderr))

@@ -20,13 +20,22 @@
 
 #include "nls.h"
 #include "nls_launch.h"
+#include "nls_runtime.h"
 #include "nls_types.h"
 
 using namespace nls;
 
-namespace {
-
+namespace nls {
+namespace rt {
 thread_local std::string g_tls_error = "";
+void set_thread_error(const std::string& m) { g_tls_error = m; }
+const char* thread_error() { return g_tls_error.c_str(); }
+}  // namespace rt
+}  // namespace nls
+
+using namespace nls::rt;
+
+namespace {
 
 struct Ticket {
   hipEvent_t start = nullptr;
@@ -36,11 +45,6 @@ struct Ticket {
   int32_t status = NLS_OK;
   uint64_t bytes = 0;  // device bytes the ticket holds until released
 };
-
-// Size bucket of the group mapping for a system of n unknowns (n > 8).
-int group_bucket(int n) { return ((n + 7) / 8) * 8 < 16 ? 16 : ((n + 7) / 8) * 8; }
-
-bool lane_mapped(int n) { return n <= 8; }
 
 }  // namespace
 
@@ -77,7 +81,7 @@ namespace {
 
 int fail(nls_context* c, int code, const std::string& msg) {
   if (c) c->last_error = msg;
-  g_tls_error = msg;
+  set_thread_error(msg);
   return code;
 }
 
@@ -85,6 +89,13 @@ int hip_fail(nls_context* c, hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return fail(c, NLS_E_DEVICE, m);
 }
+
+}  // namespace
+
+namespace nls {
+namespace rt {
+
+int group_bucket(int n) { return ((n + 7) / 8) * 8 < 16 ? 16 : ((n + 7) / 8) * 8; }
 
 int nparams_of(int family, int n) {
   if (n < 1 || n > NLS_NMAX) return -1;
@@ -266,6 +277,16 @@ int launch(int n_or_nb, bool lane, int fam, int alg, int prec, const KArgs& a, h
   return launch_group(prec, n_or_nb, fam, alg, a, st);
 }
 
+Mapping fixed_mapping(int n) {
+  if (n > 8) return Mapping{false, group_bucket(n), hipSuccess};
+  return Mapping{true, n, hipSuccess};
+}
+
+}  // namespace rt
+}  // namespace nls
+
+namespace {
+
 // dense index of an (n, family, algorithm) combination
 constexpr int kCombos = NLS_NMAX * FAM_COUNT * ALG_COUNT;
 inline int combo_index(int n, int fam, int alg) { return ((n - 1) * FAM_COUNT + fam) * ALG_COUNT + alg; }
@@ -274,12 +295,6 @@ inline void combo_split(int ci, int* n, int* fam, int* alg) {
   *fam = (ci / ALG_COUNT) % FAM_COUNT;
   *n = ci / (ALG_COUNT * FAM_COUNT) + 1;
 }
-
-struct Mapping {
-  bool lane;
-  int key_n;  // n for the lane mapping, the size bucket for the group mapping
-  hipError_t error;
-};
 
 struct Launch {
   KArgs a;
@@ -468,7 +483,7 @@ void nls_default_options(nls_alg_options* o) {
 
 const char* nls_last_error(const nls_context* c) {
   if (c) return c->last_error.c_str();
-  return g_tls_error.c_str();
+  return thread_error();
 }
 
 int nls_validate(const nls_batch* b, int64_t* first_bad) {

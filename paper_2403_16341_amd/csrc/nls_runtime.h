@@ -1,0 +1,51 @@
+// nls_runtime.h -- host-side helpers shared by the batch runtime (nls_host.cpp)
+// and the request server (nls_serve.cpp).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+
+#include "nls.h"
+#include "nls_types.h"
+
+namespace nls {
+namespace rt {
+
+// message returned by nls_last_error(NULL) on this thread
+void set_thread_error(const std::string& m);
+const char* thread_error();
+
+// parameters per system of a family at size n, or -1 if it is not defined there
+int nparams_of(int family, int n);
+// a family/size pair the kernels implement
+bool supported(int family, int n);
+// one family, size and algorithm for every system, packed back to back
+bool uniform_batch(const nls_batch* b, int* fam0, int* n0, int* alg0);
+// the (family, n, algorithm) combinations the FP32-inner form runs on
+bool fp32_inner_enabled(int fam, int n, int alg);
+
+void fill_defaults(nls_alg_options* o);
+std::string check_options(const nls_alg_options& o);
+// "" if the batch is well formed, else the reason (first_bad: offending system)
+std::string validate(const nls_batch* b, int64_t* first_bad);
+std::string check_results(const nls_results* r, int64_t M);
+KOpts to_kopts(const nls_alg_options& o);
+
+struct Mapping {
+  bool lane;
+  int key_n;  // n for the lane mapping, the size bucket for the group mapping
+  hipError_t error;
+};
+// size bucket (16, 24, ..., 64) of the group mapping for n > 8
+int group_bucket(int n);
+// the mapping used without autotuning: one system per lane for n <= 8, else
+// one system per 16/32/64-lane group
+Mapping fixed_mapping(int n);
+
+// one persistent launch; 0 on success, 1 if no kernel exists for the
+// combination, a negative hipError_t value on a launch failure
+int launch(int n_or_nb, bool lane, int fam, int alg, int prec, const KArgs& a, hipStream_t st);
+
+}  // namespace rt
+}  // namespace nls

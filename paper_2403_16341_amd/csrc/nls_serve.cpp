@@ -1,0 +1,439 @@
+// nls_serve.cpp -- the request server behind the nls_server_* entry points.
+//
+// Clients queue host-memory requests; one scheduler thread per server
+//   * reaps finished launches (event query), copies their results from the
+//     pinned mirror into the callers' arrays and releases their arena space;
+//   * admits the longest first-come-first-served prefix of the queue whose
+//     launches fit the device arena (requests with the same kernel and
+//     settings admitted together share one launch), stages their inputs in
+//     the pinned mirror and enqueues, on the least-loaded stream: one
+//     host-to-device copy of the inputs, the work-counter reset, the
+//     persistent solver launch and one device-to-host copy of the outputs,
+//     then an event.
+// Everything the device touches lives in the arena (allocated once at
+// creation), so admission and completion never call hipMalloc or hipFree.
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "nls.h"
+#include "nls_launch.h"
+#include "nls_runtime.h"
+#include "nls_serve_core.hpp"
+
+using namespace nls;
+using namespace nls::rt;
+using namespace nls::serve;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  uint64_t id = 0;
+  nls_batch b{};          // the caller's descriptor; its arrays stay caller-owned
+  nls_alg_options opts{};
+  nls_results r{};
+  int fam = 0, n = 1, alg = 0, P = 0;
+  int64_t M = 0;
+  std::string key;
+  double t_submit = 0.0, t_admit = 0.0;
+};
+
+struct InFlight {
+  PlannedLaunch plan;
+  std::vector<Req> reqs;  // in the order of plan.reqs
+  hipEvent_t ev = nullptr;
+  int stream = 0;
+  int counter = 0;
+  int32_t status = NLS_OK;
+};
+
+}  // namespace
+
+struct nls_server {
+  int device = 0;
+  int nstreams = 4;
+  int max_inflight = 256;
+  int max_admit = 256;
+  std::vector<hipStream_t> streams;
+  std::vector<double> load;  // estimated outstanding work per stream
+  char* dev = nullptr;       // device arena
+  char* host = nullptr;      // pinned host mirror (same offsets)
+  Arena arena;
+  int64_t* counters = nullptr;
+  std::vector<int> free_counters;
+  std::vector<hipEvent_t> free_events;
+  Clock::time_point t0;
+  std::list<InFlight> inflight;  // scheduler thread only
+  std::thread th;
+
+  // shared with client threads, under mu
+  std::mutex mu;
+  std::condition_variable cv_work;
+  std::condition_variable cv_done;
+  std::deque<Req> queue;
+  std::deque<nls_request_info> done;
+  bool stop = false;
+  uint64_t next_id = 1;
+  int64_t outstanding = 0;  // submitted, not yet in `done`
+  nls_server_stats st{};
+
+  double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+int sfail(int code, const std::string& m) {
+  set_thread_error(m);
+  return code;
+}
+
+// bytes of the per-request merge key: requests with equal keys run the same
+// kernel with the same settings and may share a launch
+std::string merge_key(const Req& q) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  const int32_t v[5] = {q.fam, q.n, q.alg, (int32_t)q.b.precision, q.b.maxiters};
+  put(v, sizeof v);
+  put(&q.b.abstol, sizeof q.b.abstol);
+  put(&q.opts, sizeof q.opts);
+  return k;
+}
+
+// copy a request's inputs into the pinned mirror of its launch region
+void stage_inputs(nls_server* s, const InFlight& L, const Req& q, int64_t first) {
+  char* base = s->host + L.plan.offset;
+  double* P = (double*)(base + L.plan.layout.params) + first * q.P;
+  double* U = (double*)(base + L.plan.layout.u0) + first * q.n;
+  if (q.P > 0) {
+    if (!q.b.p_offset) std::memcpy(P, q.b.params, sizeof(double) * q.M * q.P);
+    else
+      for (int64_t i = 0; i < q.M; ++i) std::memcpy(P + i * q.P, q.b.params + q.b.p_offset[i], sizeof(double) * q.P);
+  }
+  if (!q.b.u_offset) std::memcpy(U, q.b.u0, sizeof(double) * q.M * q.n);
+  else
+    for (int64_t i = 0; i < q.M; ++i) std::memcpy(U + i * q.n, q.b.u0 + q.b.u_offset[i], sizeof(double) * q.n);
+}
+
+// copy a request's outputs from the pinned mirror into the caller's arrays
+void scatter_results(nls_server* s, const InFlight& L, const Req& q, int64_t first) {
+  const char* base = s->host + L.plan.offset;
+  const Region& g = L.plan.layout;
+  const double* u = (const double*)(base + g.u) + first * q.n;
+  if (!q.b.u_offset) std::memcpy(q.r.u, u, sizeof(double) * q.M * q.n);
+  else
+    for (int64_t i = 0; i < q.M; ++i) std::memcpy(q.r.u + q.b.u_offset[i], u + i * q.n, sizeof(double) * q.n);
+  std::memcpy(q.r.fnorm_inf, (const double*)(base + g.fnorm) + first, sizeof(double) * q.M);
+  std::memcpy(q.r.iters, (const int32_t*)(base + g.iters) + first, sizeof(int32_t) * q.M);
+  std::memcpy(q.r.retcode, (const int32_t*)(base + g.retcode) + first, sizeof(int32_t) * q.M);
+  if (q.r.nfev) std::memcpy(q.r.nfev, (const int32_t*)(base + g.nfev) + first, sizeof(int32_t) * q.M);
+  if (q.r.njev) std::memcpy(q.r.njev, (const int32_t*)(base + g.njev) + first, sizeof(int32_t) * q.M);
+}
+
+// enqueue one launch: inputs in, counter reset, solve, outputs out, event
+int32_t enqueue(nls_server* s, InFlight& L) {
+  const Req& q0 = L.reqs.front();
+  const Region& g = L.plan.layout;
+  hipStream_t st = s->streams[L.stream];
+  char* d = s->dev + L.plan.offset;
+  char* h = s->host + L.plan.offset;
+  hipError_t e = hipMemcpyAsync(d, h, g.in_bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return NLS_E_DEVICE;
+  if (launch_zero_counters(s->counters + L.counter, 1, st) != 0) return NLS_E_DEVICE;
+  KArgs a{};
+  a.params = (const double*)(d + g.params);
+  a.u0 = (const double*)(d + g.u0);
+  a.u_out = (double*)(d + g.u);
+  a.fnorm = (double*)(d + g.fnorm);
+  a.iters = (int32_t*)(d + g.iters);
+  a.retcode = (int32_t*)(d + g.retcode);
+  a.nfev = (int32_t*)(d + g.nfev);
+  a.njev = (int32_t*)(d + g.njev);
+  a.counter = s->counters + L.counter;
+  a.count = L.plan.m;
+  a.P = q0.P;
+  a.n = q0.n;
+  a.maxiters = q0.b.maxiters;
+  a.abstol = q0.b.abstol;
+  a.o = to_kopts(q0.opts);
+  const Mapping mp = fixed_mapping(q0.n);
+  if (launch(mp.key_n, mp.lane, q0.fam, q0.alg, q0.b.precision, a, st) != 0) return NLS_E_DEVICE;
+  e = hipMemcpyAsync(h + g.out_off, d + g.out_off, g.out_bytes, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return NLS_E_DEVICE;
+  if (hipEventRecord(L.ev, st) != hipSuccess) return NLS_E_DEVICE;
+  return NLS_OK;
+}
+
+void complete(nls_server* s, InFlight& L) {
+  if (L.status == NLS_OK)
+    for (size_t j = 0; j < L.reqs.size(); ++j) scatter_results(s, L, L.reqs[j], L.plan.first[j]);
+  const double t = s->now_ms();
+  s->arena.release(L.plan.offset, L.plan.layout.total);
+  s->free_counters.push_back(L.counter);
+  if (L.ev) s->free_events.push_back(L.ev);
+  s->load[L.stream] -= L.plan.cost;
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (const Req& q : L.reqs) {
+    nls_request_info info{};
+    info.id = q.id;
+    info.status = L.status;
+    info.merged = (int32_t)L.reqs.size();
+    info.systems = q.M;
+    info.t_submit_ms = q.t_submit;
+    info.t_admit_ms = q.t_admit;
+    info.t_done_ms = t;
+    s->done.push_back(info);
+    s->outstanding -= 1;
+    s->st.completed += 1;
+  }
+  s->st.inflight_launches -= 1;
+  s->st.resident_bytes = s->arena.used();
+  s->cv_done.notify_all();
+}
+
+bool reap(nls_server* s) {
+  bool any = false;
+  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+    const hipError_t e = hipEventQuery(it->ev);
+    if (e == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    if (e != hipSuccess) it->status = NLS_E_DEVICE;
+    complete(s, *it);
+    it = s->inflight.erase(it);
+    any = true;
+  }
+  return any;
+}
+
+bool admit(nls_server* s) {
+  const size_t slots = (size_t)s->max_inflight - s->inflight.size();
+  if (slots == 0) return false;
+  std::vector<QueuedReq> view;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const size_t k = std::min(s->queue.size(), (size_t)s->max_admit);
+    view.reserve(k);
+    for (size_t i = 0; i < k; ++i) {
+      const Req& q = s->queue[i];
+      view.push_back(QueuedReq{q.id, q.key, q.M, q.P, q.n, (double)q.M * q.n * q.n * q.n});
+    }
+  }
+  if (view.empty()) return false;
+  std::vector<PlannedLaunch> plan = plan_admission(view, s->arena, (size_t)s->max_admit, slots);
+  if (plan.empty()) return false;
+  size_t taken = 0;
+  for (auto& L : plan) taken += L.reqs.size();
+  std::vector<Req> reqs;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (size_t i = 0; i < taken; ++i) {
+      reqs.push_back(std::move(s->queue.front()));
+      s->queue.pop_front();
+    }
+    s->st.queued = (int64_t)s->queue.size();
+  }
+  const double t_admit = s->now_ms();  // one scheduling step: one stamp
+  for (auto& P : plan) {
+    InFlight L;
+    L.plan = P;
+    for (size_t j : P.reqs) L.reqs.push_back(std::move(reqs[j]));
+    L.stream = pick_stream(s->load);
+    s->load[L.stream] += P.cost;
+    L.counter = s->free_counters.back();
+    s->free_counters.pop_back();
+    if (!s->free_events.empty()) {
+      L.ev = s->free_events.back();
+      s->free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) {
+      L.ev = nullptr;
+    }
+    for (size_t j = 0; j < L.reqs.size(); ++j) stage_inputs(s, L, L.reqs[j], P.first[j]);
+    for (Req& q : L.reqs) q.t_admit = t_admit;
+    L.status = L.ev ? enqueue(s, L) : NLS_E_DEVICE;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->st.launches += 1;
+      s->st.inflight_launches += 1;
+      s->st.resident_bytes = s->arena.used();
+      s->st.peak_resident_bytes = std::max(s->st.peak_resident_bytes, s->st.resident_bytes);
+    }
+    if (L.status != NLS_OK) {
+      // nothing (more) was enqueued for it: wait for what was, then report
+      hipStreamSynchronize(s->streams[L.stream]);
+      complete(s, L);
+      continue;
+    }
+    s->inflight.push_back(std::move(L));
+  }
+  return true;
+}
+
+void run(nls_server* s) {
+  hipSetDevice(s->device);
+  while (true) {
+    bool progressed = reap(s);
+    progressed = admit(s) || progressed;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+    if (progressed) continue;
+    if (s->inflight.empty()) {
+      // idle: sleep until a request arrives (or the server stops)
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    } else {
+      // work on the device: poll its events, waking early on a submission
+      s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+    }
+  }
+}
+
+void free_server(nls_server* s) {
+  hipSetDevice(s->device);
+  for (auto st : s->streams)
+    if (st) hipStreamSynchronize(st);
+  for (auto ev : s->free_events) hipEventDestroy(ev);
+  for (auto st : s->streams)
+    if (st) hipStreamDestroy(st);
+  if (s->counters) hipFree(s->counters);
+  if (s->dev) hipFree(s->dev);
+  if (s->host) hipHostFree(s->host);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nls_server_create(const nls_server_desc* d, nls_server** out) {
+  if (!d || !out) return sfail(NLS_E_INVALID, "nls_server_create: NULL argument");
+  const int streams = d->streams ? d->streams : 4;
+  const int max_inflight = d->max_inflight ? d->max_inflight : 256;
+  const int max_admit = d->max_admit ? d->max_admit : 256;
+  if (streams < 1 || streams > 16) return sfail(NLS_E_INVALID, "nls_server_create: streams outside 1..16");
+  if (max_inflight < 1 || max_inflight > 4096)
+    return sfail(NLS_E_INVALID, "nls_server_create: max_inflight outside 1..4096");
+  if (max_admit < 1) return sfail(NLS_E_INVALID, "nls_server_create: max_admit must be >= 1");
+  if (d->mem_budget_bytes < Arena::kAlign) return sfail(NLS_E_INVALID, "nls_server_create: mem_budget_bytes too small");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return sfail(NLS_E_DEVICE, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+  if (d->device < 0 || d->device >= ndev) return sfail(NLS_E_INVALID, "nls_server_create: bad device ordinal");
+  if ((e = hipSetDevice(d->device)) != hipSuccess) return sfail(NLS_E_DEVICE, hipGetErrorString(e));
+  nls_server* s = new nls_server();
+  s->device = d->device;
+  s->nstreams = streams;
+  s->max_inflight = max_inflight;
+  s->max_admit = max_admit;
+  s->arena.reset(d->mem_budget_bytes);
+  s->st.budget_bytes = s->arena.capacity();
+  s->t0 = Clock::now();
+  s->load.assign(streams, 0.0);
+  s->streams.assign(streams, nullptr);
+  for (int j = 0; j < streams && e == hipSuccess; ++j) e = hipStreamCreateWithFlags(&s->streams[j], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->counters, sizeof(int64_t) * max_inflight);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->dev, s->arena.capacity());
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host, s->arena.capacity(), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    const std::string m = std::string("nls_server_create: ") + hipGetErrorString(e);
+    free_server(s);
+    return sfail(e == hipErrorOutOfMemory ? NLS_E_NOMEM : NLS_E_DEVICE, m);
+  }
+  for (int i = max_inflight - 1; i >= 0; --i) s->free_counters.push_back(i);
+  s->th = std::thread(run, s);
+  *out = s;
+  return NLS_OK;
+}
+
+int nls_server_submit(nls_server* s, const nls_batch* b, const nls_results* r, uint64_t* id) {
+  if (!s || !id) return sfail(NLS_E_INVALID, "nls_server_submit: NULL argument");
+  int64_t bad = -1;
+  std::string m = validate(b, &bad);
+  if (m.empty()) m = check_results(r, b->count);
+  if (!m.empty()) return sfail(NLS_E_INVALID, m);
+  if (b->mem_kind != NLS_MEM_HOST) return sfail(NLS_E_INVALID, "server requests are host-memory batches");
+  Req q;
+  q.b = *b;
+  q.M = b->count;
+  if (r) q.r = *r;
+  fill_defaults(&q.opts);
+  if (b->opts) q.opts = *b->opts;
+  q.b.opts = nullptr;
+  q.fam = b->family ? (q.M ? b->family[0] : 0) : b->family_all;
+  q.n = b->n ? (q.M ? b->n[0] : 1) : b->n_all;
+  q.alg = b->alg ? (q.M ? b->alg[0] : 0) : b->alg_all;
+  for (int64_t i = 0; i < q.M; ++i) {
+    if ((b->family && b->family[i] != q.fam) || (b->n && b->n[i] != q.n) || (b->alg && b->alg[i] != q.alg))
+      return sfail(NLS_E_INVALID, "server requests have one family, size and algorithm");
+  }
+  q.P = nparams_of(q.fam, q.n);
+  q.key = merge_key(q);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return sfail(NLS_E_INVALID, "server is shutting down");
+  if (region_layout(q.M, q.P, q.n).total > s->arena.capacity())
+    return sfail(NLS_E_NOMEM, "request needs more device memory than the server's budget");
+  q.id = s->next_id++;
+  q.t_submit = s->now_ms();
+  *id = q.id;
+  if (q.M == 0) {
+    nls_request_info info{};
+    info.id = q.id;
+    info.status = NLS_OK;
+    info.merged = 1;
+    info.t_submit_ms = info.t_admit_ms = info.t_done_ms = q.t_submit;
+    s->done.push_back(info);
+    s->st.completed += 1;
+    s->cv_done.notify_all();
+    return NLS_OK;
+  }
+  s->queue.push_back(std::move(q));
+  s->outstanding += 1;
+  s->st.queued = (int64_t)s->queue.size();
+  s->cv_work.notify_one();
+  return NLS_OK;
+}
+
+int nls_server_poll(nls_server* s, int32_t wait_ms, nls_request_info* out, int32_t max_out, int32_t* n_out) {
+  if (!s || !n_out || (max_out > 0 && !out) || max_out < 0) return sfail(NLS_E_INVALID, "nls_server_poll: bad argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto ready = [&] { return !s->done.empty() || s->outstanding == 0; };
+  if (wait_ms < 0) s->cv_done.wait(lk, ready);
+  else if (wait_ms > 0) s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+  int32_t k = 0;
+  while (k < max_out && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n_out = k;
+  return NLS_OK;
+}
+
+int nls_server_stats_get(nls_server* s, nls_server_stats* st) {
+  if (!s || !st) return sfail(NLS_E_INVALID, "nls_server_stats_get: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *st = s->st;
+  return NLS_OK;
+}
+
+int nls_server_destroy(nls_server* s) {
+  if (!s) return NLS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  free_server(s);
+  return NLS_OK;
+}
+
+}  // extern "C"

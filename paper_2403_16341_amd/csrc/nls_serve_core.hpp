@@ -1,0 +1,206 @@
+// nls_serve_core.hpp -- the device-independent parts of the request server:
+// the arena that places resident requests inside the device-memory budget,
+// the layout of one launch's region in it, and the admission planner that
+// turns the head of the request queue into launches.  Plain C++ (offsets and
+// sizes only), so the policy runs and is tested without a device.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <iterator>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace nls {
+namespace serve {
+
+// First-fit allocator over [0, capacity) in 256-byte granules.  Free extents
+// are kept by offset and merged with their neighbours on release.
+class Arena {
+ public:
+  static constexpr uint64_t kAlign = 256;
+  explicit Arena(uint64_t capacity = 0) { reset(capacity); }
+  void reset(uint64_t capacity) {
+    cap_ = capacity / kAlign * kAlign;
+    used_ = 0;
+    free_.clear();
+    if (cap_) free_[0] = cap_;
+  }
+  static uint64_t round(uint64_t n) { return (std::max<uint64_t>(n, 1) + kAlign - 1) / kAlign * kAlign; }
+  // place n bytes; false if no free extent is large enough
+  bool alloc(uint64_t n, uint64_t* off) {
+    n = round(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const uint64_t rest = it->second - n, at = it->first + n;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += n;
+      return true;
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t n) {
+    n = round(n);
+    used_ -= n;
+    uint64_t start = off, len = n;
+    auto next = free_.lower_bound(off);
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    if (next != free_.end() && off + n == next->first) {
+      len += next->second;
+      free_.erase(next);
+    }
+    free_[start] = len;
+  }
+  uint64_t capacity() const { return cap_; }
+  uint64_t used() const { return used_; }
+  size_t extents() const { return free_.size(); }
+  uint64_t largest_free() const {
+    uint64_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  uint64_t cap_ = 0, used_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+// Byte layout of one launch's region: the inputs (parameters, then starting
+// points) and, after them, the outputs in one contiguous span so that each
+// direction is a single copy.
+struct Region {
+  uint64_t params, u0, in_bytes;  // inputs: [0, in_bytes)
+  uint64_t u, fnorm, iters, retcode, nfev, njev;
+  uint64_t out_off, out_bytes;    // outputs: [out_off, out_off + out_bytes)
+  uint64_t total;
+};
+
+inline uint64_t align16(uint64_t x) { return (x + 15) / 16 * 16; }
+
+inline Region region_layout(int64_t m, int P, int n) {
+  Region r{};
+  uint64_t o = 0;
+  r.params = o;
+  o = align16(o + 8ull * m * P);
+  r.u0 = o;
+  o = align16(o + 8ull * m * n);
+  r.in_bytes = o;
+  r.out_off = o;
+  r.u = o;
+  o = align16(o + 8ull * m * n);
+  r.fnorm = o;
+  o = align16(o + 8ull * m);
+  r.iters = o;
+  o = align16(o + 4ull * m);
+  r.retcode = o;
+  o = align16(o + 4ull * m);
+  r.nfev = o;
+  o = align16(o + 4ull * m);
+  r.njev = o;
+  o = align16(o + 4ull * m);
+  r.out_bytes = o - r.out_off;
+  r.total = o;
+  return r;
+}
+
+// A queued request as the planner sees it.  Requests with equal keys (same
+// kernel, tolerances and options) may share one launch.
+struct QueuedReq {
+  uint64_t id;
+  std::string key;
+  int64_t m;  // systems
+  int P, n;
+  double cost;  // estimated work, for stream balancing
+};
+
+struct PlannedLaunch {
+  std::string key;
+  std::vector<size_t> reqs;      // positions in the queue, in arrival order
+  std::vector<int64_t> first;    // first system of each request inside the launch
+  int64_t m = 0;
+  int P = 0, n = 0;
+  double cost = 0.0;
+  Region layout{};
+  uint64_t offset = 0;           // placement in the arena
+};
+
+// Admission: the longest prefix of the queue (first come, first served; at
+// most max_reqs requests and max_launches new launches) whose launches can
+// all be placed in the arena at once.  Requests of the prefix with equal keys
+// are merged into one launch.  The head request blocks the rest when it does
+// not fit, so large requests are never starved.  The launches are placed in
+// the arena on return; an empty result means nothing fits until memory is
+// released.
+inline std::vector<PlannedLaunch> plan_admission(const std::vector<QueuedReq>& q, Arena& arena,
+                                                 size_t max_reqs, size_t max_launches) {
+  std::vector<PlannedLaunch> best;
+  std::vector<PlannedLaunch> cur;
+  std::map<std::string, size_t> at;
+  const size_t limit = std::min(q.size(), max_reqs);
+  for (size_t i = 0; i < limit; ++i) {
+    const QueuedReq& r = q[i];
+    auto it = at.find(r.key);
+    if (it == at.end()) {
+      if (cur.size() >= max_launches) break;
+      PlannedLaunch L;
+      L.key = r.key;
+      L.P = r.P;
+      L.n = r.n;
+      at[r.key] = cur.size();
+      cur.push_back(L);
+      it = at.find(r.key);
+    }
+    PlannedLaunch& L = cur[it->second];
+    L.reqs.push_back(i);
+    L.first.push_back(L.m);
+    L.m += r.m;
+    L.cost += r.cost;
+    L.layout = region_layout(L.m, L.P, L.n);
+    // can every launch of the prefix be placed at once?  (largest first on a
+    // copy of the arena; the same order is used for the real placement)
+    std::vector<size_t> ord(cur.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](size_t a, size_t b) { return cur[a].layout.total > cur[b].layout.total; });
+    Arena trial = arena;
+    bool fits = true;
+    for (size_t k : ord) {
+      uint64_t off;
+      if (!trial.alloc(cur[k].layout.total, &off)) { fits = false; break; }
+      cur[k].offset = off;
+    }
+    if (!fits) break;
+    best = cur;
+  }
+  // commit the placement of the accepted prefix
+  std::vector<size_t> ord(best.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](size_t a, size_t b) { return best[a].layout.total > best[b].layout.total; });
+  for (size_t k : ord) {
+    uint64_t off = 0;
+    arena.alloc(best[k].layout.total, &off);
+    best[k].offset = off;
+  }
+  return best;
+}
+
+// Index of the least-loaded stream (ties: lowest index).
+inline int pick_stream(const std::vector<double>& load) {
+  return (int)(std::min_element(load.begin(), load.end()) - load.begin());
+}
+
+}  // namespace serve
+}  // namespace nls

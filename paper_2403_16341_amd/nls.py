@@ -32,7 +32,9 @@ CTX_AUTOTUNE = 2
 
 # every symbol include/nls.h declares
 EXPORTS = ("nls_create", "nls_destroy", "nls_solve_batch", "nls_query", "nls_validate",
-           "nls_last_error", "nls_get_mapping", "nls_nparams", "nls_default_options", "nls_abi_version")
+           "nls_last_error", "nls_get_mapping", "nls_nparams", "nls_default_options", "nls_abi_version",
+           "nls_server_create", "nls_server_submit", "nls_server_poll", "nls_server_stats_get",
+           "nls_server_destroy")
 
 
 class ContextDesc(ctypes.Structure):
@@ -69,6 +71,25 @@ class Results(ctypes.Structure):
 class TicketInfo(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("gpu_ms", ctypes.c_double),
                 ("systems", ctypes.c_int64)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("max_admit", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("merged", ctypes.c_int32),
+                ("systems", ctypes.c_int64), ("t_submit_ms", ctypes.c_double),
+                ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("inflight_launches", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_uint64), ("peak_resident_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64)]
 
 
 class NLSError(RuntimeError):
@@ -112,6 +133,18 @@ def lib() -> ctypes.CDLL:
     L.nls_default_options.restype = None
     L.nls_abi_version.argtypes = []
     L.nls_abi_version.restype = ctypes.c_int
+    L.nls_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]
+    L.nls_server_create.restype = ctypes.c_int
+    L.nls_server_submit.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Results),
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.nls_server_submit.restype = ctypes.c_int
+    L.nls_server_poll.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestInfo), ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.nls_server_poll.restype = ctypes.c_int
+    L.nls_server_stats_get.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.nls_server_stats_get.restype = ctypes.c_int
+    L.nls_server_destroy.argtypes = [P]
+    L.nls_server_destroy.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -296,3 +329,99 @@ def solve_host(ctx: Context, b: "_inputs.Batch", precision: int | None = None, o
                       mem_kind=MEM_HOST, out=out)
     ctx.query(t, -1)
     return out
+
+
+class Server:
+    """An ``nls_server``: continuous batching of host-memory solve requests.
+
+    ``submit`` queues a request (an ``inputs.Batch`` of one family, size and
+    algorithm) and returns its id; the arrays of a request are held here until
+    ``poll`` reports it, together with its results and host-clock stamps."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 1 << 30, streams: int = 4,
+                 max_inflight: int = 0, max_admit: int = 0):
+        L = lib()
+        d = ServerDesc(device, streams, mem_budget_bytes, max_inflight, max_admit)
+        h = ctypes.c_void_p()
+        rc = L.nls_server_create(ctypes.byref(d), ctypes.byref(h))
+        if rc != OK:
+            raise NLSError(rc, last_error(None))
+        self.handle = h
+        self._live = {}
+
+    def submit(self, b: "_inputs.Batch", precision: int | None = None, opts=None) -> int:
+        M = b.M
+        uni = b.uniform() if M else (FAMILY_CUBIC, 1, ALG_NEWTON)
+        if uni is None:
+            raise NLSError(E_INVALID, "server requests have one family, size and algorithm")
+        fam, n, alg = uni
+        P = nls_params(fam, n)
+        packed = (np.array_equal(b.p_off, np.arange(M + 1) * P)
+                  and np.array_equal(b.u_off, np.arange(M + 1) * n))
+        po = None if packed else np.ascontiguousarray(b.p_off, dtype=np.int64)
+        uo = None if packed else np.ascontiguousarray(b.u_off, dtype=np.int64)
+        params = np.ascontiguousarray(b.params) if b.params.size else np.zeros(1)
+        u0 = np.ascontiguousarray(b.u0)
+        out = dict(u=u0.copy(), fnorm_inf=np.empty(M), iters=np.empty(M, np.int32),
+                   retcode=np.empty(M, np.int32), nfev=np.empty(M, np.int32), njev=np.empty(M, np.int32))
+        bb = Batch()
+        bb.count = M
+        bb.family_all, bb.n_all, bb.alg_all = fam, n, alg
+        bb.precision = int(b.precision if precision is None else precision)
+        bb.mem_kind = MEM_HOST
+        bb.maxiters = int(b.maxiters)
+        bb.abstol = float(b.abstol)
+        bb.params, bb.u0 = _ptr(params), _ptr(u0)
+        bb.p_offset, bb.u_offset = _ptr(po), _ptr(uo)
+        if opts is not None:
+            bb.opts = ctypes.pointer(opts)
+        r = Results(*[_ptr(out[k]) for k in ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev")])
+        i = ctypes.c_uint64(0)
+        rc = lib().nls_server_submit(self.handle, ctypes.byref(bb), ctypes.byref(r), ctypes.byref(i))
+        if rc != OK:
+            raise NLSError(rc, last_error(None))
+        self._live[i.value] = (out, (params, u0, po, uo, opts))
+        return i.value
+
+    def poll(self, wait_ms: int = 0, max_out: int = 256) -> list:
+        """Completed requests as (info dict, results dict), oldest completion first."""
+        buf = (RequestInfo * max_out)()
+        k = ctypes.c_int32(0)
+        rc = lib().nls_server_poll(self.handle, int(wait_ms), buf, max_out, ctypes.byref(k))
+        if rc != OK:
+            raise NLSError(rc, last_error(None))
+        done = []
+        for j in range(k.value):
+            x = buf[j]
+            info = dict(id=x.id, status=x.status, merged=x.merged, systems=x.systems,
+                        t_submit_ms=x.t_submit_ms, t_admit_ms=x.t_admit_ms, t_done_ms=x.t_done_ms)
+            out, _keep = self._live.pop(x.id)
+            done.append((info, out))
+        return done
+
+    def drain(self) -> list:
+        """Wait for every outstanding request; returns them as ``poll`` does."""
+        done = []
+        while self._live:
+            done += self.poll(-1)
+        return done
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        lib().nls_server_stats_get(self.handle, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nls_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nls_params(family: int, n: int) -> int:
+    return lib().nls_nparams(family, n)
