@@ -14,8 +14,10 @@
 // creation), so admission and completion never call hipMalloc or hipFree.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -64,6 +66,7 @@ struct nls_server {
   int nstreams = 4;
   int max_inflight = 256;
   int max_admit = 256;
+  double slice_work = 0.0;  // no slicing unless NLS_SERVE_SLICE_WORK > 0
   std::vector<hipStream_t> streams;
   std::vector<double> load;  // estimated outstanding work per stream
   char* dev = nullptr;       // device arena
@@ -148,25 +151,31 @@ int32_t enqueue(nls_server* s, InFlight& L) {
   char* h = s->host + L.plan.offset;
   hipError_t e = hipMemcpyAsync(d, h, g.in_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return NLS_E_DEVICE;
-  if (launch_zero_counters(s->counters + L.counter, 1, st) != 0) return NLS_E_DEVICE;
-  KArgs a{};
-  a.params = (const double*)(d + g.params);
-  a.u0 = (const double*)(d + g.u0);
-  a.u_out = (double*)(d + g.u);
-  a.fnorm = (double*)(d + g.fnorm);
-  a.iters = (int32_t*)(d + g.iters);
-  a.retcode = (int32_t*)(d + g.retcode);
-  a.nfev = (int32_t*)(d + g.nfev);
-  a.njev = (int32_t*)(d + g.njev);
-  a.counter = s->counters + L.counter;
-  a.count = L.plan.m;
-  a.P = q0.P;
-  a.n = q0.n;
-  a.maxiters = q0.b.maxiters;
-  a.abstol = q0.b.abstol;
-  a.o = to_kopts(q0.opts);
   const Mapping mp = fixed_mapping(q0.n);
-  if (launch(mp.key_n, mp.lane, q0.fam, q0.alg, q0.b.precision, a, st) != 0) return NLS_E_DEVICE;
+  const int64_t step = slice_systems(q0.n, s->slice_work);
+  for (int64_t s0 = 0; s0 < L.plan.m; s0 += step) {
+    // one slice: systems s0 .. s0 + cnt - 1 of the launch (its own counter
+    // reset; slices on one stream run one after the other)
+    const int64_t cnt = std::min<int64_t>(step, L.plan.m - s0);
+    if (launch_zero_counters(s->counters + L.counter, 1, st) != 0) return NLS_E_DEVICE;
+    KArgs a{};
+    a.params = (const double*)(d + g.params) + s0 * q0.P;
+    a.u0 = (const double*)(d + g.u0) + s0 * q0.n;
+    a.u_out = (double*)(d + g.u) + s0 * q0.n;
+    a.fnorm = (double*)(d + g.fnorm) + s0;
+    a.iters = (int32_t*)(d + g.iters) + s0;
+    a.retcode = (int32_t*)(d + g.retcode) + s0;
+    a.nfev = (int32_t*)(d + g.nfev) + s0;
+    a.njev = (int32_t*)(d + g.njev) + s0;
+    a.counter = s->counters + L.counter;
+    a.count = cnt;
+    a.P = q0.P;
+    a.n = q0.n;
+    a.maxiters = q0.b.maxiters;
+    a.abstol = q0.b.abstol;
+    a.o = to_kopts(q0.opts);
+    if (launch(mp.key_n, mp.lane, q0.fam, q0.alg, q0.b.precision, a, st) != 0) return NLS_E_DEVICE;
+  }
   e = hipMemcpyAsync(h + g.out_off, d + g.out_off, g.out_bytes, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return NLS_E_DEVICE;
   if (hipEventRecord(L.ev, st) != hipSuccess) return NLS_E_DEVICE;
@@ -226,7 +235,7 @@ bool admit(nls_server* s) {
     view.reserve(k);
     for (size_t i = 0; i < k; ++i) {
       const Req& q = s->queue[i];
-      view.push_back(QueuedReq{q.id, q.key, q.M, q.P, q.n, (double)q.M * q.n * q.n * q.n});
+      view.push_back(QueuedReq{q.id, q.key, q.M, q.P, q.n, launch_work(q.M, q.n)});
     }
   }
   if (view.empty()) return false;
@@ -248,7 +257,7 @@ bool admit(nls_server* s) {
     InFlight L;
     L.plan = P;
     for (size_t j : P.reqs) L.reqs.push_back(std::move(reqs[j]));
-    L.stream = pick_stream(s->load);
+    L.stream = pick_stream(s->load, P.cost);
     s->load[L.stream] += P.cost;
     L.counter = s->free_counters.back();
     s->free_counters.pop_back();
@@ -334,6 +343,10 @@ int nls_server_create(const nls_server_desc* d, nls_server** out) {
   s->nstreams = streams;
   s->max_inflight = max_inflight;
   s->max_admit = max_admit;
+  if (const char* w = std::getenv("NLS_SERVE_SLICE_WORK")) {
+    const double v = std::atof(w);
+    if (v > 0) s->slice_work = v;
+  }
   s->arena.reset(d->mem_budget_bytes);
   s->st.budget_bytes = s->arena.capacity();
   s->t0 = Clock::now();

@@ -197,9 +197,36 @@ inline std::vector<PlannedLaunch> plan_admission(const std::vector<QueuedReq>& q
   return best;
 }
 
-// Index of the least-loaded stream (ties: lowest index).
-inline int pick_stream(const std::vector<double>& load) {
-  return (int)(std::min_element(load.begin(), load.end()) - load.begin());
+// Slicing: a launch whose work (systems x n^3) exceeds a bound may run as
+// several persistent launches in a row on its stream; between two of them the
+// device's dispatcher hands freed compute units to other streams' launches.
+// Off by default: each slice ends with its slowest system, which costs more
+// throughput than the latency it saves (measured on the serving workload).
+constexpr int64_t kNoSlice = int64_t(1) << 60;  // more systems than any launch
+
+// Systems per slice for size n under the bound slice_work (<= 0: no slicing):
+// a multiple of 64, at least 64.
+inline int64_t slice_systems(int n, double slice_work) {
+  if (!(slice_work > 0)) return kNoSlice;
+  const double n3 = (double)n * n * n;
+  const double m = slice_work / n3;
+  if (m >= (double)kNoSlice) return kNoSlice;
+  const int64_t k = (int64_t)m / 64 * 64;
+  return k < 64 ? 64 : k;
+}
+
+inline double launch_work(int64_t m, int n) { return (double)m * n * n * n; }
+
+// Launches up to this much work (systems x n^3; e.g. 16k systems at n = 16,
+// 256 at n = 64) may use stream 0; larger ones never do.
+constexpr double kExpressWork = 67108864.0;  // 2^26
+
+// Stream for a launch: the least-loaded one (ties: lowest index).  With more
+// than one stream, stream 0 is kept for small launches, so a small request
+// never waits behind a large one in stream order.
+inline int pick_stream(const std::vector<double>& load, double work, double express_work = kExpressWork) {
+  const size_t first = (load.size() > 1 && work > express_work) ? 1 : 0;
+  return (int)(std::min_element(load.begin() + first, load.end()) - load.begin());
 }
 
 }  // namespace serve

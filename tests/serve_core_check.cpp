@@ -236,7 +236,32 @@ static void check_simulation() {
   }
 }
 
+static void check_slices_and_streams() {
+  for (double w : {67108864.0, 1e6, 1e9, 1e20}) {
+    int64_t prev = INT64_MAX;
+    for (int n = 1; n <= 64; ++n) {
+      const int64_t m = slice_systems(n, w);
+      CHECK(m >= 64 && m % 64 == 0, "slice of %lld systems at n=%d", (long long)m, n);
+      CHECK(m == 64 || launch_work(m, n) <= w, "slice work above the bound at n=%d", n);
+      CHECK(m == 64 || w > 1e12 || launch_work(m + 64, n) > w, "slice not maximal at n=%d", n);
+      CHECK(m <= prev, "slices grow with n");
+      prev = m;
+    }
+  }
+  CHECK(slice_systems(16, 67108864.0) == 16384 && slice_systems(64, 67108864.0) == 256, "slices at 2^26");
+  CHECK(slice_systems(8, 0.0) == kNoSlice && slice_systems(64, -1.0) == kNoSlice, "slicing off");
+  // stream 0 takes only small launches
+  std::vector<double> load = {0.0, 5.0, 3.0, 3.0};
+  CHECK(pick_stream(load, 10.0) == 0, "small work goes to the idle express stream");
+  CHECK(pick_stream(load, kExpressWork * 2) == 2, "large work skips stream 0 (ties: lowest index)");
+  load[0] = 9.0;
+  CHECK(pick_stream(load, 10.0) == 2, "small work goes to the least-loaded stream");
+  std::vector<double> one = {7.0};
+  CHECK(pick_stream(one, kExpressWork * 2) == 0, "a single stream takes everything");
+}
+
 int main() {
+  check_slices_and_streams();
   check_arena();
   check_layout();
   check_planner();

@@ -166,3 +166,21 @@ def test_server_offsets_empty_and_refusals(nls, requests):
         srv.submit(c24, precision=inputs.PREC_FP32_INNER)
     assert ei.value.code == nls.E_INVALID
     srv.close()
+
+
+def test_server_sliced_launches(nls, requests, monkeypatch):
+    """With slicing switched on (NLS_SERVE_SLICE_WORK, read at server
+    creation) every launch of more than 64 systems runs as several persistent
+    launches; results stay bitwise those of the direct batch path."""
+    monkeypatch.setenv("NLS_SERVE_SLICE_WORK", "65536")
+    print("case: sliced launches, 12 requests", flush=True)
+    srv = nls.Server(0, mem_budget_bytes=128 << 20)
+    ids = {srv.submit(rq.batch): rq for rq in requests[:12]}
+    done = srv.drain()
+    srv.close()
+    ctx = nls.Context(0)
+    for info, out in done:
+        rq = ids[info["id"]]
+        ref = nls.results_to_numpy(ctx.solve(nls.DeviceBatch(rq.batch)))
+        assert info["status"] == 0 and _same(out, ref), rq.rid
+    ctx.close()
