@@ -239,62 +239,38 @@ def serving_leg(nls, args):
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--systems", type=int, default=1 << 20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the tanh N=16 and mixed workloads")
-    ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
-    ap.add_argument("--serve-payloads", type=int, default=64, help="distinct request payloads")
-    ap.add_argument("--serve-stream", type=int, default=256, help="requests per open-loop stream")
-    ap.add_argument("--serve-load", type=lambda x: [float(v) for v in x.split(",")], default=[0.5, 0.8],
-                    help="open-loop arrival rates as fractions of the closed-loop capacity")
-    ap.add_argument("--serve-budget-gib", type=int, default=8, help="server device-memory budget")
-    ap.add_argument("--forms", default="fp64,fp32", help="precision forms to time (profiling runs)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
-              "(--gpus 1); multi-GPU runs are not part of it", file=sys.stderr)
-        sys.exit(2)
+def run_leg(leg, args, timeout):
+    """Run `bench.py --leg LEG` as a child process; its stderr streams through,
+    its one stdout line is the leg's JSON.  A failure or time-out is recorded
+    instead of the numbers."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--leg", leg,
+           "--steps", str(args.steps), "--warmup", str(args.warmup), "--systems", str(args.systems),
+           "--serve-payloads", str(args.serve_payloads), "--serve-stream", str(args.serve_stream),
+           "--serve-load", ",".join(str(x) for x in args.serve_load),
+           "--serve-budget-gib", str(args.serve_budget_gib)]
+    print("[bench] leg %s: child process, limit %.0f s" % (leg, timeout), file=sys.stderr, flush=True)
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=timeout)
+    except subprocess.TimeoutExpired:
+        print("[bench] leg %s: stopped after %.0f s" % (leg, timeout), file=sys.stderr, flush=True)
+        return {"error": "timed out after %.0f s" % timeout}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": "exit status %d" % r.returncode}
+    return json.loads(lines[-1])
 
+
+def headline_leg(nls, args):
+    """The headline workload: FP64 and FP32-inner forms, flop model, roofline."""
     import torch
-    from paper_2403_16341_amd import inputs, nls
-
-    if args.copy_calibration:
-        # a plain copy kernel of known size: reads and writes MIB MiB each launch
-        n = args.copy_calibration * (1 << 20) // 8
-        x = torch.ones(n, dtype=torch.float64, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(10):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 10}))
-        return
-
+    from paper_2403_16341_amd import inputs
     b = inputs.config(2, M=args.systems)
     M, n = b.M, 8
     print("[bench] workload %s: %d systems, generated" % (b.name, M), file=sys.stderr, flush=True)
     ctx = nls.Context(0)
     db = nls.DeviceBatch(b)
     torch.cuda.synchronize()
-
-    forms = args.forms.split(",")
-    if forms == ["fp64"]:
-        # profiling run: time the plain form only and stop
-        out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
-        print("[bench] fp64: %.3f ms/step, kernel %.3f ms" % (step64 * 1e3, np.mean(gpu64)), file=sys.stderr)
-        ctx.close()
-        return
-    if forms == ["fp32"]:
-        out32, step32, gpu32 = run_form(nls, ctx, db, inputs.PREC_FP32_INNER, args.steps, args.warmup)
-        print("[bench] fp32-inner: %.3f ms/step, kernel %.3f ms" % (step32 * 1e3, np.mean(gpu32)), file=sys.stderr)
-        ctx.close()
-        return
     out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
     rc64 = out64["retcode"].cpu().numpy()
     conv64 = int((rc64 == 0).sum())
@@ -315,11 +291,12 @@ def main():
     u64 = out64["u"].view(M, n)
     u32 = out32["u"].view(M, n)
     rel = ((u32 - u64).abs().amax(dim=1) / u64.abs().amax(dim=1).clamp_min(1e-300)).cpu().numpy()
+    ctx.close()
 
     kernel_ms = float(np.mean(gpu64))
     bytes_per_system = 8 * (n * n + n) + 8 * n + 8 * n + 8 + 4 + 4  # A, b, u0 in; u, ||F||, iters, rc out
     achieved = bytes_per_system * M / (kernel_ms * 1e-3) / 1e9
-    res = {
+    return {
         "metric": "converged solves/s, N=8 1M batch, FP64 vs FP32-inner; serving p50/p99 latency",
         "value": conv64 / step64,
         "unit": "solves/s",
@@ -348,25 +325,99 @@ def main():
         "retcodes_fp64": np.bincount(rc64, minlength=7).tolist(),
     }
 
-    if not args.no_extra:
-        res["workloads"] = extra_workloads(nls, ctx, args)
 
-    if not args.no_serving:
-        res["serving"] = serving_leg(nls, args)
+def cpu_baseline(args):
+    """The oracle on the headline workload, on up to 16 host threads."""
+    import oracle
+    from paper_2403_16341_amd import inputs
+    b = inputs.config(2, M=args.systems)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    r = oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off, b.abstol,
+                           b.maxiters, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": float((r["retcode"] == 0).sum()) / dt, "unit": "solves/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "all %d systems of the workload, single-threaded FP64 oracle per system on %d "
+                      "threads over contiguous chunks (%.2f s)" % (b.M, cores, dt)}
 
-    if not args.no_cpu_baseline:
-        import oracle
-        cores = min(len(os.sched_getaffinity(0)), 16)
-        t0 = time.perf_counter()
-        r = oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off, b.abstol,
-                               b.maxiters, nthreads=cores)
-        dt = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": float((r["retcode"] == 0).sum()) / dt, "unit": "solves/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": "all %d systems of the workload, single-threaded FP64 oracle per "
-                                         "system on %d threads over contiguous chunks (%.2f s)" % (M, cores, dt)}
-    ctx.close()
-    print(json.dumps(res), flush=True)
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--systems", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the tanh N=16 and mixed workloads")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--serve-payloads", type=int, default=64, help="distinct request payloads")
+    ap.add_argument("--serve-stream", type=int, default=256, help="requests per open-loop stream")
+    ap.add_argument("--serve-load", type=lambda x: [float(v) for v in x.split(",")], default=[0.5, 0.8],
+                    help="open-loop arrival rates as fractions of the closed-loop capacity")
+    ap.add_argument("--serve-budget-gib", type=int, default=8, help="server device-memory budget")
+    ap.add_argument("--leg", choices=("headline", "extras", "serving"), default=None,
+                    help="run one leg in this process and print its JSON")
+    ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
+              "(--gpus 1); multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    if args.leg is None and not args.forms and not args.copy_calibration:
+        # orchestrator: never touches the GPU itself; every GPU leg runs in a
+        # child process with a time limit, so a failing secondary leg cannot
+        # cost the headline line
+        res = run_leg("headline", args, timeout=400.0)
+        if "error" in res:
+            print(json.dumps({"metric": "converged solves/s, N=8 1M batch, FP64 vs FP32-inner; serving "
+                                        "p50/p99 latency", "value": None, "error": res["error"]}), flush=True)
+            sys.exit(1)
+        if not args.no_extra:
+            res["workloads"] = run_leg("extras", args, timeout=165.0)
+        if not args.no_serving:
+            res["serving"] = run_leg("serving", args, timeout=165.0)
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline(args)
+        print(json.dumps(res), flush=True)
+        return
+
+    import torch
+    from paper_2403_16341_amd import inputs, nls
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes MIB MiB each launch
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 10}))
+        return
+
+    if args.forms:
+        # profiling run: time one form in this process and stop
+        b = inputs.config(2, M=args.systems)
+        ctx = nls.Context(0)
+        db = nls.DeviceBatch(b)
+        torch.cuda.synchronize()
+        prec = inputs.PREC_FP64 if args.forms == "fp64" else inputs.PREC_FP32_INNER
+        _, step, gpu = run_form(nls, ctx, db, prec, args.steps, args.warmup)
+        print("[bench] %s: %.3f ms/step, kernel %.3f ms" % (args.forms, step * 1e3, np.mean(gpu)), file=sys.stderr)
+        ctx.close()
+        return
+
+    if args.leg == "headline":
+        out = headline_leg(nls, args)
+    else:
+        ctx = nls.Context(0)
+        out = extra_workloads(nls, ctx, args) if args.leg == "extras" else serving_leg(nls, args)
+        ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

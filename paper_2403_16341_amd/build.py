@@ -27,7 +27,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE,
 # device code: no packed FP32 instructions (some of their forms have given
 # wrong results on gfx950 without any error); FMA contraction allowed
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-ffp-contract=fast"]
+          "-ffp-contract=fast",
+          # the group kernels unroll their LU fully up to n = 64 (row arrays in
+          # registers); the default limit for requested unrolling stops at 40
+          "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 GROUP_BUCKETS = (16, 24, 32, 40, 48, 56, 64)
 SOURCES = [

@@ -355,6 +355,13 @@ template <int N, int FAM> struct LaneParams {
 
 enum : int { ST_IDLE = 0, ST_DIR = 1, ST_TRIAL = 2 };
 
+// Most main-loop trips one system can take: every trip evaluates one trial
+// point, and a system evaluates at most maxiters directions with at most
+// max_halvings + 1 trial points each (one per trial for dogleg and Newton).
+__device__ __forceinline__ int64_t trip_limit(int32_t maxit, int32_t mh) {
+  return (int64_t)maxit * ((int64_t)(mh > 0 ? mh : 0) + 1) + 4;
+}
+
 // Chunk staging.  Lane l copies the P parameters and the N starting values of
 // system l of the chunk from global memory into LDS "column" l: a region of
 // K doubles is laid out as 16-byte granules (granule g of lane l at byte
@@ -440,6 +447,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   const double rho_bt = a.o.armijo_rho;
   const int32_t mh = a.o.armijo_max_halvings;
   const DoglegOpts o = a.o.dogleg();
+  const int64_t trip_cap = trip_limit(maxit, mh);
 
   // chunk currently being handed out (wave-uniform): from the device-wide
   // counter when there is one, else blockIdx.x, blockIdx.x + gridDim.x, ...
@@ -463,6 +471,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   // per-lane state
   int st = ST_IDLE;
   int64_t s = 0, uo = 0;
+  int64_t trips = 0;  // main-loop trips on the current system
   int32_t k = 0, nf = 0, nj = 0, m = 0;
   double alpha = 1.0, phi0 = 0.0, Delta = o.delta0;
   // ||F||_inf (+inf if F is not finite) and ||F||_2^2 of the current iterate,
@@ -536,6 +545,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         nf = 1;
         nj = 0;
         k = 0;
+        trips = 0;
         Delta = o.delta0;
         st = ST_DIR;
         const bool fin0 = all_finite(F);
@@ -547,6 +557,12 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       }
     }
     if (__all(st == ST_IDLE) && chunk >= nchunks) break;
+    // no system needs more trips than trip_cap: past it, end the system as
+    // invalid rather than loop (iters = -1 - k, fnorm = trips)
+    if (st != ST_IDLE && ++trips > trip_cap) {
+      fcur = (double)trips;
+      finish(RC_INVALID, -1 - k);
+    }
 
     // ---------------- direction (lanes that need one) ----------------
     if (ALG == ALG_DOGLEG && st != ST_IDLE) ++k;  // every trial is an iteration
@@ -748,100 +764,171 @@ template <int L> __device__ __forceinline__ bool grp_any(bool pred) {
   return (b & mask) != 0ull;
 }
 
+// Per-wavefront LDS of the group mapping.  A holds the coefficient matrix of
+// each group's current system (dense families), rows padded to NB + 2
+// doubles: 16-byte aligned rows whose stride spreads a group's row reads over
+// distinct banks.
 template <int NB, int L, typename TI> struct GroupShared {
   static constexpr int G = 64 / L;
-  // per-component arrays are sized by the group width L so that every lane
-  // (including lanes r >= n that own no row) has a slot of its own
-  double x[G][L];        // evaluation point
-  double aux[G][L];      // tanh of the evaluation point (tanh family)
-  double dphi[G][L];     // dual derivative of the column map at the current u
+  static constexpr int AS = NB + 2;  // row stride of A in doubles
+  double x[G][L];        // evaluation point, or the column map at it (tanh)
+  double fv[G][L];       // F at the current iterate (for J^T F)
+  double dphi[G][L];     // dual derivative of the column map at the iterate
   TI piv[G][NB + 2];     // pivot row of the current elimination step + RHS
   TI sol[G][L];          // solution of the triangular solves
   TI gv[G][L];           // g = J^T F
 };
-template <int NB, int L, typename TI> struct GroupSharedT {
+template <int NB, int L, bool HAS_A> struct GroupA {
   static constexpr int G = 64 / L;
-  TI t[G][L][NB];        // products J_ij F_i for the column sums of J^T F
+  double a[G][NB][NB + 2];
 };
-// algorithms without a gradient need no transpose buffer
-template <int NB, int L> struct GroupSharedT<NB, L, char> {
-  char t[1];
+template <int NB, int L> struct GroupA<NB, L, false> {
+  double a[1][1][2];
 };
 
 template <int NB, int FAM> struct RowFam;
 
-template <int NB> struct RowFam<NB, FAM_CUBIC> {
-  double A[NB];
-  double b;
-  __device__ __forceinline__ void load(const double* __restrict__ p, int n, int r, bool own) {
+// Copy the n x n matrix at p into the group's LDS rows (zero outside n x n):
+// consecutive lanes read consecutive doubles of a row.
+template <int NB, int L>
+__device__ __forceinline__ void stage_matrix(double (&a)[NB][NB + 2], const double* __restrict__ p, int n, int r) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) A[j] = (own && j < n) ? p[r * n + j] : 0.0;
+  for (int e = 0; e < (NB * NB) / L; ++e) {
+    const int idx = e * L + r;
+    const int i = idx / NB, j = idx % NB;
+    a[i][j] = (i < n && j < n) ? p[i * n + j] : 0.0;
+  }
+}
+
+// sum_j a_rj v_j over the NB columns of an LDS row (zeros beyond n), in column
+// order, with 16-byte reads of both operands
+template <int NB>
+__device__ __forceinline__ double row_dot(const double* __restrict__ arow, const double* __restrict__ v) {
+  const double2* a2 = reinterpret_cast<const double2*>(arow);
+  const double2* v2 = reinterpret_cast<const double2*>(v);
+  double2 a0 = a2[0], v0 = v2[0];
+  double s = a0.x * v0.x;
+  s = __builtin_fma(a0.y, v0.y, s);
+#pragma unroll
+  for (int h = 1; h < NB / 2; ++h) {
+    const double2 ah = a2[h], vh = v2[h];
+    s = __builtin_fma(ah.x, vh.x, s);
+    s = __builtin_fma(ah.y, vh.y, s);
+  }
+  return s;
+}
+
+// sum_i a_ir w_i down column r (zeros beyond n), in row order
+template <int NB>
+__device__ __forceinline__ double col_dot(const double (&a)[NB][NB + 2], int r, const double* __restrict__ w) {
+  double s = a[0][r] * w[0];
+#pragma unroll
+  for (int i = 1; i < NB; ++i) s = __builtin_fma(a[i][r], w[i], s);
+  return s;
+}
+
+template <int NB> struct RowFam<NB, FAM_CUBIC> {
+  static constexpr bool HAS_A = true;
+  double b;
+  template <int L>
+  __device__ __forceinline__ void load(GroupA<NB, L, true>& A, int gi, const double* __restrict__ p, int n, int r,
+                                       bool own) {
+    stage_matrix<NB, L>(A.a[gi], p, n, r);
     b = own ? p[n * n + r] : 0.0;
   }
-  // F_r = sum_j A_rj x_j + 0.1 x_r^3 - b_r   (x read from LDS)
+  // F_r = sum_j A_rj x_j + 0.1 x_r^3 - b_r
   template <int L, typename TI>
-  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                             double xr, double& auxr) const {
-    sh.x[gi][r] = xr;
+  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                             bool own, double xr, double& auxr) const {
+    sh.x[gi][r] = own ? xr : 0.0;
     wave_sync();
-    double s = A[0] * sh.x[gi][0];
-#pragma unroll
-    for (int j = 1; j < NB; ++j) s = __builtin_fma(A[j], sh.x[gi][j], s);
+    const double s = row_dot<NB>(A.a[gi][r], sh.x[gi]);
     auxr = 0.0;
     wave_sync();
     return own ? (s + 0.1 * (xr * xr * xr)) - b : 0.0;
   }
+  // row r: A_rj, plus the dual derivative of 0.1 u_r^3 on the diagonal
   template <int L, typename TI>
-  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                               double ur, double, TI (&J)[NB]) const {
+  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                               bool own, double ur, double, TI (&J)[NB]) const {
     const double diag = cubic_term_deriv(ur);
+    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][r]);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) J[j] = (TI)((j == r && own) ? A[j] + diag : A[j]);
+    for (int h = 0; h < NB / 2; ++h) {
+      const double2 v = a2[h];
+      J[2 * h] = (TI)((2 * h == r && own) ? v.x + diag : v.x);
+      J[2 * h + 1] = (TI)((2 * h + 1 == r && own) ? v.y + diag : v.y);
+    }
+  }
+  // (J^T F)_r = sum_i A_ir F_i + c'(u_r) F_r with J = A + diag(c'(u))
+  template <int L, typename TI>
+  __device__ __forceinline__ double jt_times(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                             bool own, double ur, double, double Fr) const {
+    sh.fv[gi][r] = own ? Fr : 0.0;
+    wave_sync();
+    const double s = own ? col_dot<NB>(A.a[gi], r, sh.fv[gi]) : 0.0;
+    wave_sync();
+    return own ? __builtin_fma(cubic_term_deriv(ur), Fr, s) : 0.0;
   }
 };
 
 template <int NB> struct RowFam<NB, FAM_TANH> {
-  double A[NB];
+  static constexpr bool HAS_A = true;
   double b, beta;
-  __device__ __forceinline__ void load(const double* __restrict__ p, int n, int r, bool own) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j) A[j] = (own && j < n) ? p[r * n + j] : 0.0;
+  template <int L>
+  __device__ __forceinline__ void load(GroupA<NB, L, true>& A, int gi, const double* __restrict__ p, int n, int r,
+                                       bool own) {
+    stage_matrix<NB, L>(A.a[gi], p, n, r);
     b = own ? p[n * n + r] : 0.0;
     beta = p[n * n + n];
   }
   // F_r = sum_j A_rj tanh(x_j) + beta x_r - b_r; lane j computes tanh(x_j)
   template <int L, typename TI>
-  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                             double xr, double& auxr) const {
+  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                             bool own, double xr, double& auxr) const {
     auxr = own ? tanh(xr) : 0.0;
-    sh.aux[gi][r] = auxr;
+    sh.x[gi][r] = auxr;
     wave_sync();
-    double s = A[0] * sh.aux[gi][0];
-#pragma unroll
-    for (int j = 1; j < NB; ++j) s = __builtin_fma(A[j], sh.aux[gi][j], s);
+    const double s = row_dot<NB>(A.a[gi][r], sh.x[gi]);
     wave_sync();
     return own ? (s + beta * xr) - b : 0.0;
   }
   // J_rj = A_rj tanh'(u_j) + beta [r == j]; tanh'(u_j) from the dual tanh of lane j
   template <int L, typename TI>
-  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                               double ur, double auxr, TI (&J)[NB]) const {
+  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                               bool own, double ur, double auxr, TI (&J)[NB]) const {
     sh.dphi[gi][r] = own ? dtanh_known(dseed(ur), auxr).d : 0.0;
     wave_sync();
+    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][r]);
+    const double2* d2 = reinterpret_cast<const double2*>(sh.dphi[gi]);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double v = A[j] * sh.dphi[gi][j];
-      J[j] = (TI)((j == r && own) ? v + beta : v);
+    for (int h = 0; h < NB / 2; ++h) {
+      const double2 v = a2[h], dv = d2[h];
+      const double v0 = v.x * dv.x, v1 = v.y * dv.y;
+      J[2 * h] = (TI)((2 * h == r && own) ? v0 + beta : v0);
+      J[2 * h + 1] = (TI)((2 * h + 1 == r && own) ? v1 + beta : v1);
     }
     wave_sync();
+  }
+  // (J^T F)_r = tanh'(u_r) sum_i A_ir F_i + beta F_r
+  template <int L, typename TI>
+  __device__ __forceinline__ double jt_times(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
+                                             bool own, double ur, double auxr, double Fr) const {
+    sh.fv[gi][r] = own ? Fr : 0.0;
+    wave_sync();
+    const double s = own ? col_dot<NB>(A.a[gi], r, sh.fv[gi]) : 0.0;
+    wave_sync();
+    return own ? __builtin_fma(beta, Fr, dtanh_known(dseed(ur), auxr).d * s) : 0.0;
   }
 };
 
 template <int NB> struct RowFam<NB, FAM_ROSENBROCK> {
-  __device__ __forceinline__ void load(const double* __restrict__, int, int, bool) {}
+  static constexpr bool HAS_A = false;
+  template <int L>
+  __device__ __forceinline__ void load(GroupA<NB, L, false>&, int, const double* __restrict__, int, int, bool) {}
   template <int L, typename TI>
-  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                             double xr, double& auxr) const {
+  __device__ __forceinline__ double residual(GroupShared<NB, L, TI>& sh, GroupA<NB, L, false>&, int gi, int r,
+                                             bool own, double xr, double& auxr) const {
     sh.x[gi][r] = xr;
     wave_sync();
     const double xm = (own && r > 0) ? sh.x[gi][r - 1] : 0.0;
@@ -850,30 +937,52 @@ template <int NB> struct RowFam<NB, FAM_ROSENBROCK> {
     if (!own) return 0.0;
     return r == 0 ? 1.0 - xr : 10.0 * (xr - xm * xm);
   }
+  // row r of the dual Jacobian: seeds on u_{r-1} and u_r (1 - u_0 for r = 0)
+  __device__ __forceinline__ static void row_derivs(int r, double ur, double um, double& dm, double& dd) {
+    dm = (10.0 * (dconst(ur) - dseed(um) * dseed(um))).d;
+    dd = r == 0 ? (dconst(1.0) - dseed(ur)).d : (10.0 * (dseed(ur) - dconst(um) * dconst(um))).d;
+  }
   template <int L, typename TI>
-  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, int gi, int r, bool own,
-                                               double ur, double, TI (&J)[NB]) const {
+  __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, GroupA<NB, L, false>&, int gi, int r,
+                                               bool own, double ur, double, TI (&J)[NB]) const {
     sh.x[gi][r] = ur;
     wave_sync();
     const double um = (own && r > 0) ? sh.x[gi][r - 1] : 0.0;
     wave_sync();
-    // 10 (u_r - u_{r-1}^2) with seeds on u_{r-1} and on u_r; 1 - u_0 for r = 0
-    const Dual<double> dm = 10.0 * (dconst(ur) - dseed(um) * dseed(um));
-    const Dual<double> dd = r == 0 ? dconst(1.0) - dseed(ur) : 10.0 * (dseed(ur) - dconst(um) * dconst(um));
+    double dm, dd;
+    row_derivs(r, ur, um, dm, dd);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       double v = 0.0;
-      v = (j == r) ? dd.d : v;
-      v = (j == r - 1) ? dm.d : v;
+      v = (j == r) ? dd : v;
+      v = (j == r - 1) ? dm : v;
       J[j] = (TI)(own ? v : 0.0);
     }
+  }
+  // (J^T F)_r = J_rr F_r + J_{r+1,r} F_{r+1}: lane r + 1 hands over its
+  // sub-diagonal product
+  template <int L, typename TI>
+  __device__ __forceinline__ double jt_times(GroupShared<NB, L, TI>& sh, GroupA<NB, L, false>&, int gi, int r,
+                                             bool own, double ur, double, double Fr) const {
+    sh.x[gi][r] = ur;
+    wave_sync();
+    const double um = (own && r > 0) ? sh.x[gi][r - 1] : 0.0;
+    wave_sync();
+    double dm, dd;
+    row_derivs(r, ur, um, dm, dd);
+    sh.fv[gi][r] = (own && r > 0) ? dm * Fr : 0.0;  // J_{r,r-1} F_r, for lane r - 1
+    wave_sync();
+    const double below = (r + 1 < L) ? sh.fv[gi][r + 1] : 0.0;
+    wave_sync();
+    return own ? dd * Fr + below : 0.0;
   }
 };
 
 // LU with partial pivoting of the group's rows (logical positions instead of
-// row exchanges), RHS carried along, then back substitution.  On return the
-// solution component r is in sh.sol[gi][r].  Returns false (group-uniform) on
-// a zero or non-finite pivot.
+// row exchanges), RHS carried along, then back substitution.  Both loops are
+// unrolled fully (see the unroll threshold in the build), so every row index
+// is a constant and the row stays in registers.  On return the solution component r is in
+// sh.sol[gi][r].  Returns false (group-uniform) on a zero or non-finite pivot.
 template <int NB, int L, typename TI>
 __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
                                                TI (&J)[NB], TI rhs) {
@@ -939,15 +1048,17 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
 // Persistent group-mapping kernel.  Each group of L lanes solves one system at
 // a time and, when it finishes, takes the next system from a device-wide
 // counter (a.counter, zeroed before the launch) or, without a counter, the
-// next one of its static stride.  Every trip runs the factorisation for the
-// groups that need a new direction, then one residual evaluation for every
-// group holding a trial point; groups diverge freely, and all cross-lane
+// next one of its static stride; the system's matrix is copied into the
+// group's LDS rows when it is taken.  Every trip runs the factorisation for
+// the groups that need a new direction, then one residual evaluation for
+// every group holding a trial point; groups diverge freely, and all cross-lane
 // traffic stays inside a group.
 template <int NB, int L, int FAM, int ALG, typename TI>
 __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   constexpr int G = 64 / L;
-  __shared__ GroupShared<NB, L, TI> sh;
-  __shared__ GroupSharedT<NB, L, typename std::conditional<ALG == ALG_DOGLEG, TI, char>::type> st;
+  constexpr bool HAS_A = RowFam<NB, FAM>::HAS_A;
+  __shared__ __attribute__((aligned(16))) GroupShared<NB, L, TI> sh;
+  __shared__ __attribute__((aligned(16))) GroupA<NB, L, HAS_A> sa;
   const int lane = threadIdx.x;
   const int gi = lane / L;
   const int r = lane % L;
@@ -959,9 +1070,11 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   const DoglegOpts o = a.o.dogleg();
   const int64_t total_groups = (int64_t)gridDim.x * G;
   int64_t next_static = (int64_t)blockIdx.x * G + gi;
+  const int64_t trip_cap = trip_limit(maxit, mh);
 
   // per-group state (every lane of a group holds the same copy)
   int gst = ST_IDLE;
+  int64_t trips = 0;  // main-loop trips on the current system
   bool exhausted = false;
   int64_t s = 0, uo = 0;
   int n = 0;
@@ -1011,12 +1124,14 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
         n = a.nsys ? (int)a.nsys[s] : a.n;
         own = r < n;
         uo = a.u_off ? a.u_off[s] : s * (int64_t)n;
-        fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P), n, r, own);
+        fam.template load<L>(sa, gi, a.params + (a.p_off ? a.p_off[s] : s * a.P), n, r, own);
         u = own ? a.u0[uo + r] : 0.0;
-        F = fam.template residual<L, TI>(sh, gi, r, own, u, aux);
+        wave_sync();
+        F = fam.template residual<L, TI>(sh, sa, gi, r, own, u, aux);
         nf = 1;
         nj = 0;
         k = 0;
+        trips = 0;
         Delta = o.delta0;
         gst = ST_DIR;
         const bool fin0 = set_norms();
@@ -1026,13 +1141,19 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
       }
     }
     if (!__any(!(gst == ST_IDLE && exhausted))) break;
+    // no system needs more trips than trip_cap: past it, end the system as
+    // invalid rather than loop (iters = -1 - k, fnorm = trips)
+    if (gst != ST_IDLE && ++trips > trip_cap) {
+      fcur = (double)trips;
+      finish(RC_INVALID, -1 - k);
+    }
 
     // ---------------- direction (groups that need one) ----------------
     if (ALG == ALG_DOGLEG && gst != ST_IDLE) ++k;  // every trial is an iteration
     if (gst == ST_DIR) {
       if (ALG != ALG_DOGLEG) ++k;
       TI J[NB];
-      fam.template jacobian_row<L, TI>(sh, gi, r, own, u, aux, J);
+      fam.template jacobian_row<L, TI>(sh, sa, gi, r, own, u, aux, J);
       ++nj;
       if constexpr (ALG != ALG_DOGLEG) {
         if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, (TI)(-F))) {
@@ -1047,16 +1168,8 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
         }
       } else {
         const TI Ff = (TI)F;
-        // g_j = sum_i J_ij F_i: row products through LDS, column sums in row order
-#pragma unroll
-        for (int j = 0; j < NB; ++j) st.t[gi][r][j] = J[j] * Ff;
-        wave_sync();
-        TI gs = TI(0);
-        if (own) {
-          gs = st.t[gi][0][r];
-          for (int i = 1; i < n; ++i) gs += st.t[gi][i][r];
-        }
-        g = gs;
+        // g = J^T F (steepest-descent direction of 0.5 ||F||^2) and J g
+        g = (TI)fam.template jt_times<L, TI>(sh, sa, gi, r, own, u, aux, F);
         sh.gv[gi][r] = own ? g : TI(0);
         wave_sync();
         TI jg = J[0] * sh.gv[gi][0];
@@ -1117,7 +1230,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
         ut = u + step;
       }
       double auxt = 0.0;
-      const double Ft = fam.template residual<L, TI>(sh, gi, r, own, ut, auxt);
+      const double Ft = fam.template residual<L, TI>(sh, sa, gi, r, own, ut, auxt);
       ++nf;
       const bool fin_t = !grp_any<L>(!finite64(Ft));
       const double phit = grp_sum<L>(Ft * Ft);
