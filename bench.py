@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--leg", choices=("headline", "extras", "serving"), default=None,
                     help="run one leg in this process and print its JSON")
     ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")
+    ap.add_argument("--workload", choices=("headline", "tanh16"), default="headline",
+                    help="profiling: the batch --forms times (the headline, or 2^18 x N=16 tanh dogleg)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
     args = ap.parse_args()
@@ -401,7 +403,7 @@ def main():
 
     if args.forms:
         # profiling run: time one form in this process and stop
-        b = inputs.config(2, M=args.systems)
+        b = inputs.config(2, M=args.systems) if args.workload == "headline" else inputs.config(3)
         ctx = nls.Context(0)
         db = nls.DeviceBatch(b)
         torch.cuda.synchronize()

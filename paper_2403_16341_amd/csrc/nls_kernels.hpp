@@ -1075,6 +1075,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   // per-group state (every lane of a group holds the same copy)
   int gst = ST_IDLE;
   int64_t trips = 0;  // main-loop trips on the current system
+  bool split = false; // a lane's copy of the state disagreed with the leader's
   bool exhausted = false;
   int64_t s = 0, uo = 0;
   int n = 0;
@@ -1091,8 +1092,8 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
     if (own) a.u_out[uo + r] = u;
     if (r == 0) {
       a.fnorm[s] = fcur;
-      a.iters[s] = iters;
-      a.retcode[s] = rc;
+      a.iters[s] = split ? -100000 : iters;
+      a.retcode[s] = split ? RC_INVALID : rc;
       if (a.nfev) a.nfev[s] = nf;
       if (a.njev) a.njev[s] = nj;
     }
@@ -1106,8 +1107,21 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   };
 
   while (true) {
+    // The group's state is uniform by construction (every decision is taken
+    // on group reductions or LDS broadcasts); the leader's copy (lane 0 of
+    // the group) is made authoritative at every trip, so that lanes can never
+    // refill on their own without advancing the work counter.  A lane that
+    // disagreed marks the system (retcode invalid, iters -100000).
+    {
+      const int lead_st = __shfl(gst, gi * L, 64);
+      const int lead_ex = __shfl((int)exhausted, gi * L, 64);
+      split = split || grp_any<L>(gst != lead_st || (int)exhausted != lead_ex);
+      gst = lead_st;
+      exhausted = lead_ex != 0;
+    }
     // ---------------- retire / refill (idle groups) ----------------
     if (gst == ST_IDLE && !exhausted) {
+      split = false;
       int64_t t;
       if (a.counter) {
         int64_t mine = 0;
