@@ -114,9 +114,7 @@ def extra_workloads(nls, ctx, args):
         db = nls.DeviceBatch(b)
         torch.cuda.synchronize()
         entry = {"systems": b.M}
-        forms = ((inputs.PREC_FP64, "fp64"), (inputs.PREC_FP32_INNER, "fp32_inner")) if k == 3 else \
-            ((inputs.PREC_FP64, "fp64"),)   # FP32-inner mixed batches are switched off in this build
-        for prec, pname in forms:
+        for prec, pname in ((inputs.PREC_FP64, "fp64"), (inputs.PREC_FP32_INNER, "fp32_inner")):
             o, step, gms = run_form(nls, ctx, db, prec, 3, 1, with_counters=True)
             rc = o["retcode"].cpu().numpy()
             conv = int((rc == 0).sum())

@@ -76,11 +76,7 @@ extern "C" {
  * FP64       : everything in binary64.
  * FP32_INNER : Jacobian, LU factor/solve and the dogleg step algebra in
  *              binary32; residual, norms, acceptance tests and the update
- *              u += delta stay binary64 (Newton acts as iterative refinement).
- *              Accepted for uniform batches (one family, n and algorithm)
- *              of the cubic family with n <= 8 under Newton or Armijo, and
- *              of the tanh family with 9 <= n <= 16 under dogleg; other
- *              batches fail with NLS_E_INVALID. */
+ *              u += delta stay binary64 (Newton acts as iterative refinement). */
 #define NLS_PREC_FP64 0
 #define NLS_PREC_FP32_INNER 1
 

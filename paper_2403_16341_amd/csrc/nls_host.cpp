@@ -136,11 +136,6 @@ bool uniform_batch(const nls_batch* b, int* fam0, int* n0, int* alg0) {
   return true;
 }
 
-bool fp32_inner_enabled(int fam, int n, int alg) {
-  if (fam == NLS_FAMILY_CUBIC) return n <= 8 && (alg == NLS_ALG_NEWTON || alg == NLS_ALG_NEWTON_ARMIJO);
-  if (fam == NLS_FAMILY_TANH) return n >= 9 && n <= 16 && alg == NLS_ALG_DOGLEG;
-  return false;
-}
 
 void fill_defaults(nls_alg_options* o) {
   o->armijo_c = 1e-4;
@@ -234,17 +229,6 @@ std::string validate(const nls_batch* b, int64_t* first_bad) {
   (void)utotal;
   if (!b->u0) return "u0 is NULL";
   if (ptotal > 0 && !b->params) return "params is NULL";
-  // FP32-inner runs only on the kernels it has been verified with on the
-  // device: uniform, packed cubic batches with n <= 8 under Newton or Armijo,
-  // and uniform, packed tanh dogleg batches with 9 <= n <= 16.  Everything
-  // else stays off until the stall seen on a mixed FP32-inner batch is
-  // explained.
-  if (b->precision == NLS_PREC_FP32_INNER) {
-    int fam0, n0, alg0;
-    if (!uniform_batch(b, &fam0, &n0, &alg0) || !fp32_inner_enabled(fam0, n0, alg0))
-      return "FP32-inner precision is limited to uniform cubic batches with n <= 8 (Newton, Armijo) "
-             "and uniform tanh dogleg batches with 9 <= n <= 16 in this build";
-  }
   return "";
 }
 

@@ -746,14 +746,54 @@ namespace nls {
 // bucket NB are handled with a runtime n <= NB: rows and columns n..NB-1 are
 // zero and never take part in a pivot search.
 // ---------------------------------------------------------------------------
+// Partner value at butterfly level M of a group reduction.  Inside a row of
+// 16 lanes the partners come from DPP lane moves (quad permutations for
+// M = 1, 2; half-row and row mirrors for M = 4, 8), which pair every lane
+// with one lane of the other half of its current block, as an exclusive-or
+// butterfly does; across rows (M = 16, 32) from a backward permute.  Every
+// combine below is symmetric, so all lanes of a group end with the same bits.
+enum : int { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141 };
+template <int CTRL> __device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int M, int L> __device__ __forceinline__ int grp_partner(int v) {
+  if constexpr (M == 1) return dpp_move<DPP_QUAD_XOR1>(v);
+  else if constexpr (M == 2) return dpp_move<DPP_QUAD_XOR2>(v);
+  else if constexpr (M == 4) return dpp_move<DPP_ROW_HALF_MIRROR>(v);
+  else if constexpr (M == 8) return dpp_move<DPP_ROW_MIRROR>(v);
+  else return __shfl_xor(v, M, L);
+}
+template <int M, int L> __device__ __forceinline__ float grp_partner(float v) {
+  return __int_as_float(grp_partner<M, L>(__float_as_int(v)));
+}
+template <int M, int L> __device__ __forceinline__ double grp_partner(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = grp_partner<M, L>((int)(b & 0xffffffffll));
+  const int hi = grp_partner<M, L>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// apply f(M) for the levels M = 1, 2, 4, ... < L in increasing order
+template <int L, typename F> __device__ __forceinline__ void grp_levels(F&& f) {
+  f(std::integral_constant<int, 1>{});
+  f(std::integral_constant<int, 2>{});
+  f(std::integral_constant<int, 4>{});
+  f(std::integral_constant<int, 8>{});
+  if constexpr (L > 16) f(std::integral_constant<int, 16>{});
+  if constexpr (L > 32) f(std::integral_constant<int, 32>{});
+}
+// Sum over the group.  The opaque copy makes v a rounded value before the
+// first addition: without it the compiler may fuse that addition with the
+// multiply that produced v (as in grp_sum(x * y)), and a fused
+// x_i y_i + rnd(x_j y_j) is not symmetric in i and j -- the lanes of a group
+// would end with sums that differ in the last bits, and decisions taken on
+// them could split the group.
 template <int L, typename T> __device__ __forceinline__ T grp_sum(T v) {
-#pragma unroll
-  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, L);
+  __asm__ volatile("" : "+v"(v));
+  grp_levels<L>([&](auto mc) { v += grp_partner<decltype(mc)::value, L>(v); });
   return v;
 }
 template <int L, typename T> __device__ __forceinline__ T grp_max(T v) {
-#pragma unroll
-  for (int m = 1; m < L; m <<= 1) v = fmax(v, __shfl_xor(v, m, L));
+  grp_levels<L>([&](auto mc) { v = fmax(v, grp_partner<decltype(mc)::value, L>(v)); });
   return v;
 }
 // true if pred holds on any lane of this lane's group
@@ -1000,14 +1040,14 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
       const bool nan_at_k = grp_any<L>(pos == k && v != v);
       TI key = cand ? (v != v ? TI(-1) : __builtin_fabs(v)) : TI(-2);
       int kp = pos;
-#pragma unroll
-      for (int m = 1; m < L; m <<= 1) {
-        const TI ok_ = __shfl_xor(key, m, L);
-        const int op = __shfl_xor(kp, m, L);
+      grp_levels<L>([&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        const TI ok_ = grp_partner<M, L>(key);
+        const int op = grp_partner<M, L>(kp);
         const bool take = ok_ > key || (ok_ == key && op < kp);
         key = take ? ok_ : key;
         kp = take ? op : kp;
-      }
+      });
       // the pivot row publishes columns k.. and its RHS
       if (pos == kp) {
 #pragma unroll

@@ -22,8 +22,6 @@ int nparams_of(int family, int n);
 bool supported(int family, int n);
 // one family, size and algorithm for every system, packed back to back
 bool uniform_batch(const nls_batch* b, int* fam0, int* n0, int* alg0);
-// the (family, n, algorithm) combinations the FP32-inner form runs on
-bool fp32_inner_enabled(int fam, int n, int alg);
 
 void fill_defaults(nls_alg_options* o);
 std::string check_options(const nls_alg_options& o);

@@ -114,9 +114,7 @@ def test_nonfinite_maxiters_and_empty(nls, ctx):
 
 
 def test_host_and_device_paths_agree_and_repeat_bitwise(nls, ctx):
-    # (the 900-system version of this batch stalled on the device with no
-    # cause found; it stays off the GPU)
-    b = inputs.config(4, M=700)
+    b = inputs.config(4, M=900)
     g1 = run_gpu(nls, ctx, b)
     g2 = run_gpu(nls, ctx, b)
     h = nls.solve_host(ctx, b)
@@ -204,10 +202,8 @@ def test_group_mapping_for_small_systems(nls, monkeypatch):
         for k, M in ((1, 300), (2, 333)):
             b = inputs.config(k, M=M)
             compare(b, run_gpu(nls, c, b), "group-mapped workload %d" % k)
-        # (the 900-system version of this batch stalled twice on the device
-        # with no cause found; it stays off the GPU)
-        b = inputs.config(4, M=700)
-        compare(b, run_gpu(nls, c, b), "group-mapped mixed", max_other_root=14)
+        b = inputs.config(4, M=900)
+        compare(b, run_gpu(nls, c, b), "group-mapped mixed", max_other_root=18)
     finally:
         c.close()
 
@@ -229,21 +225,22 @@ def test_autotuned_mixed_batch(nls):
         c.close()
 
 
-def test_fp32_inner_mixed_batches_are_rejected(nls, ctx):
-    """FP32-inner stays off for mixed batches and for kernels it has not been
-    verified with: the call fails before any device work and leaves the
-    outputs untouched."""
-    b = inputs.config(4, M=200)
-    db = nls.DeviceBatch(b)
-    out = db.alloc_results()
-    for v in out.values():
-        v.fill_(7)
-    with pytest.raises(nls.NLSError) as ei:
-        ctx.solve(db, out=out, precision=inputs.PREC_FP32_INNER)
-    assert ei.value.code == nls.E_INVALID and "FP32-inner" in str(ei.value)
-    assert all(bool((v == 7).all()) for v in out.values())
-    for fam, n, alg in ((inputs.TANH, 8, inputs.DOGLEG), (inputs.CUBIC, 24, inputs.ARMIJO)):
-        bb = inputs.homogeneous(fam, n, alg, np.zeros((4, inputs.nparams(fam, n))), np.zeros((4, n)),
-                                1e-10, 10)
-        with pytest.raises(nls.NLSError):
-            ctx.solve(nls.DeviceBatch(bb), precision=inputs.PREC_FP32_INNER)
+def test_fp32_inner_mixed_batch(nls, ctx):
+    """FP32-inner on the mixed workload (every lane and group kernel in FP32
+    form, one graph of launches): every GPU success meets the stopping test in
+    FP64, the cubic systems (unique roots) reach the oracle's root, and tanh
+    systems mostly reach the same root as the FP64 oracle."""
+    b = inputs.config(4, M=1500)
+    g = run_gpu(nls, ctx, b, precision=inputs.PREC_FP32_INNER)
+    o = run_oracle(b)
+    assert (g["retcode"] != nls.RC_INVALID).all()
+    succ = g["retcode"] == oracle.RC_SUCCESS
+    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+    cub = b.family == inputs.CUBIC
+    assert succ[cub].all()
+    errs = np.array([rel_err(b, g["u"], o["u"], s) for s in np.nonzero(cub)[0]])
+    assert errs.max() <= 1e-8, errs.max()
+    both = succ & (o["retcode"] == oracle.RC_SUCCESS) & ~cub
+    errs = np.array([rel_err(b, g["u"], o["u"], s) for s in np.nonzero(both)[0]])
+    print("fp32-inner mixed: tanh same root %d of %d" % ((errs <= 1e-8).sum(), both.sum()), flush=True)
+    assert (errs <= 1e-8).sum() >= 0.9 * both.sum()

@@ -149,7 +149,7 @@ def test_server_offsets_empty_and_refusals(nls, requests):
         assert np.array_equal(g[k], r[k])
 
     # refusals: larger than the whole budget, several sizes in one request,
-    # a precision form that is switched off for the combination
+    # a size outside 1..64
     small = nls.Server(0, mem_budget_bytes=1 << 16)
     big = inputs.homogeneous(inputs.CUBIC, 8, inputs.ARMIJO, np.zeros((2000, 72)), np.zeros((2000, 8)),
                              1e-10, 10)
@@ -161,9 +161,9 @@ def test_server_offsets_empty_and_refusals(nls, requests):
     if mixed.uniform() is None:
         with pytest.raises(nls.NLSError):
             srv.submit(mixed)
-    c24 = inputs.homogeneous(inputs.CUBIC, 24, inputs.ARMIJO, np.zeros((2, 600)), np.zeros((2, 24)), 1e-10, 10)
+    c70 = inputs.homogeneous(inputs.CUBIC, 70, inputs.ARMIJO, np.zeros((2, 70 * 71)), np.zeros((2, 70)), 1e-10, 10)
     with pytest.raises(nls.NLSError) as ei:
-        srv.submit(c24, precision=inputs.PREC_FP32_INNER)
+        srv.submit(c70)
     assert ei.value.code == nls.E_INVALID
     srv.close()
 
