@@ -166,7 +166,7 @@ def serving_leg(nls, args):
     (the same request alone in the queue vs in the mix)."""
     from paper_2403_16341_amd import inputs
     t0 = time.perf_counter()
-    pool = inputs.serving_requests(args.serve_payloads, rate_hz=1.0, precision=inputs.PREC_FP64)
+    pool = inputs.serving_requests(args.serve_payloads, rate_hz=1.0, precision=inputs.PREC_FP32_INNER)
     print("[bench] serving: %d request payloads generated (%.1f s), %d systems"
           % (len(pool), time.perf_counter() - t0, sum(r.batch.M for r in pool)), file=sys.stderr, flush=True)
     srv = nls.Server(0, mem_budget_bytes=args.serve_budget_gib << 30, streams=4)

@@ -228,7 +228,7 @@ class Request:
 
 def serving_requests(count: int, rate_hz: float, seed: int = SEED_BASE * 100,
                      max_systems: int = 65536, n_range=(2, 64),
-                     precision: int = PREC_FP64) -> list:
+                     precision: int = PREC_FP32_INNER) -> list:
     """Poisson arrivals; request size log-uniform on [1, max_systems]; N ~ U{lo..hi}
     per request; family 50/50 (cubic with Newton+Armijo, tanh with dogleg).
     Request r draws its payload from seed ``seed + r``."""

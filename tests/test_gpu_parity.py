@@ -244,3 +244,31 @@ def test_fp32_inner_mixed_batch(nls, ctx):
     errs = np.array([rel_err(b, g["u"], o["u"], s) for s in np.nonzero(both)[0]])
     print("fp32-inner mixed: tanh same root %d of %d" % ((errs <= 1e-8).sum(), both.sum()), flush=True)
     assert (errs <= 1e-8).sum() >= 0.9 * both.sum()
+
+@pytest.mark.parametrize("fam,alg", [(inputs.CUBIC, inputs.NEWTON), (inputs.CUBIC, inputs.ARMIJO),
+                                     (inputs.TANH, inputs.ARMIJO), (inputs.TANH, inputs.DOGLEG)])
+@pytest.mark.parametrize("n", [3, 8, 12, 24, 40, 64])
+def test_fp32_inner_grid(nls, ctx, fam, alg, n):
+    """FP32-inner on every mapping (lane, 16/32/64-lane groups): every GPU
+    success passes the FP64 stopping test; cubic systems (unique roots) reach
+    the FP64 oracle's root; tanh successes mostly reach the oracle's root."""
+    rng = np.random.Generator(np.random.PCG64(3000 + 10 * n + fam))
+    M = 70 if n <= 16 else 23
+    if fam == inputs.CUBIC:
+        p, u0 = inputs.cubic_params(rng, M, n), rng.uniform(-3, 3, (M, n))
+    else:
+        p, u0 = inputs.tanh_params(rng, M, n), rng.uniform(-4, 4, (M, n))
+    b = inputs.homogeneous(fam, n, alg, p, u0, 1e-10, 40)
+    print("case: fp32-inner fam=%d alg=%d n=%d" % (fam, alg, n), flush=True)
+    g = run_gpu(nls, ctx, b, precision=inputs.PREC_FP32_INNER)
+    o = run_oracle(b)
+    assert (g["retcode"] != nls.RC_INVALID).all()
+    succ = g["retcode"] == oracle.RC_SUCCESS
+    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+    both = succ & (o["retcode"] == oracle.RC_SUCCESS)
+    errs = np.array([rel_err(b, g["u"], o["u"], s) for s in np.nonzero(both)[0]])
+    if fam == inputs.CUBIC:
+        assert (succ == (o["retcode"] == oracle.RC_SUCCESS)).all()
+        assert errs.max() <= 1e-8, errs.max()
+    else:
+        assert (errs <= 1e-8).sum() >= 0.8 * both.sum(), ((errs <= 1e-8).sum(), both.sum())

@@ -31,7 +31,8 @@ def nls():
 def requests():
     # sizes up to 300 systems, n in 2..40: every mapping (lane, 16/32/64-lane
     # groups), both families, Armijo and dogleg
-    return inputs.serving_requests(24, rate_hz=0.0, seed=777000, max_systems=300, n_range=(2, 40))
+    return inputs.serving_requests(24, rate_hz=0.0, seed=777000, max_systems=300, n_range=(2, 40),
+                                   precision=inputs.PREC_FP64)
 
 
 def _same(a, b):
@@ -184,3 +185,27 @@ def test_server_sliced_launches(nls, requests, monkeypatch):
         ref = nls.results_to_numpy(ctx.solve(nls.DeviceBatch(rq.batch)))
         assert info["status"] == 0 and _same(out, ref), rq.rid
     ctx.close()
+
+
+def test_server_fp32_inner_alone_vs_mix(nls):
+    """FP32-inner requests (the serving workload's form): each request's
+    results are bitwise the same alone and in a mix, and every success passes
+    the FP64 stopping test."""
+    reqs = inputs.serving_requests(12, rate_hz=0.0, seed=778000, max_systems=200, n_range=(2, 64),
+                                   precision=inputs.PREC_FP32_INNER)
+    print("case: 12 fp32-inner requests alone, then mixed", flush=True)
+    srv = nls.Server(0, mem_budget_bytes=128 << 20)
+    alone = {}
+    for rq in reqs:
+        srv.submit(rq.batch)
+        (info, out), = srv.drain()
+        alone[rq.rid] = out
+    ids = {srv.submit(rq.batch): rq for rq in reqs}
+    done = srv.drain()
+    srv.close()
+    for info, out in done:
+        rq = ids[info["id"]]
+        assert info["status"] == 0 and _same(out, alone[rq.rid]), rq.rid
+        succ = out["retcode"] == 0
+        assert (out["retcode"] != nls.RC_INVALID).all()
+        assert (out["fnorm_inf"][succ] <= rq.batch.abstol).all()
