@@ -357,8 +357,9 @@ def main():
     ap.add_argument("--leg", choices=("headline", "extras", "serving"), default=None,
                     help="run one leg in this process and print its JSON")
     ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")
-    ap.add_argument("--workload", choices=("headline", "tanh16"), default="headline",
-                    help="profiling: the batch --forms times (the headline, or 2^18 x N=16 tanh dogleg)")
+    ap.add_argument("--workload", choices=("headline", "tanh16", "cubic64", "cubic40"), default="headline",
+                    help="profiling: the batch --forms times (the headline, 2^18 x N=16 tanh dogleg, or "
+                         "16,384 x N=64 / N=40 cubic Armijo)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
     args = ap.parse_args()
@@ -401,7 +402,15 @@ def main():
 
     if args.forms:
         # profiling run: time one form in this process and stop
-        b = inputs.config(2, M=args.systems) if args.workload == "headline" else inputs.config(3)
+        if args.workload == "headline":
+            b = inputs.config(2, M=args.systems)
+        elif args.workload == "tanh16":
+            b = inputs.config(3)
+        else:
+            nn = 64 if args.workload == "cubic64" else 40
+            rng = np.random.Generator(np.random.PCG64(7000 + nn))
+            b = inputs.homogeneous(inputs.CUBIC, nn, inputs.ARMIJO, inputs.cubic_params(rng, 16384, nn),
+                                   rng.uniform(-3.0, 3.0, (16384, nn)), 1e-10, 100)
         ctx = nls.Context(0)
         db = nls.DeviceBatch(b)
         torch.cuda.synchronize()
