@@ -270,6 +270,41 @@ static int newton_direction(int family, int n, const double* p, const double* u,
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* POLY (Sec. 3.2, default poly-algorithm): for small systems the default     */
+/* chain skips the quasi-Newton phase and tries Newton-Raphson, then Newton   */
+/* with a line search, then a trust-region method, moving on when one fails.  */
+/* Readings: each attempt restarts from u0 with the full budget; the first    */
+/* success ends the chain; when all fail the smallest final ||F||_inf wins    */
+/* (the earliest attempt on ties); the counters add up over the attempts.     */
+/* ------------------------------------------------------------------------ */
+static or_result solve_poly(int family, int n, const double* p, const double* u0, double abstol,
+                            int32_t maxiters, const or_opts* o, double* u_out) {
+  static const int chain[3] = {OR_ALG_NEWTON, OR_ALG_ARMIJO, OR_ALG_DOGLEG};
+  double ut[OR_NMAX];
+  or_result best, r;
+  int32_t iters = 0, nfev = 0, njev = 0;
+  int a, have = 0;
+  best.retcode = OR_RC_MAXITERS; best.iters = 0; best.nfev = 0; best.njev = 0;
+  best.fnorm_inf = INFINITY;
+  for (a = 0; a < 3; ++a) {
+    r = or_solve_one(family, n, chain[a], p, u0, abstol, maxiters, o, ut, NULL, 0, NULL);
+    iters += r.iters;
+    nfev += r.nfev;
+    njev += r.njev;
+    if (!have || r.retcode == OR_RC_SUCCESS || r.fnorm_inf < best.fnorm_inf) {
+      best = r;
+      memcpy(u_out, ut, sizeof(double) * n);
+      have = 1;
+    }
+    if (r.retcode == OR_RC_SUCCESS) break;
+  }
+  best.iters = iters;
+  best.nfev = nfev;
+  best.njev = njev;
+  return best;
+}
+
 or_result or_solve_one(int family, int n, int alg, const double* p, const double* u0,
                        double abstol, int32_t maxiters, const or_opts* o_in, double* u_out,
                        double* trace, int32_t trace_cap, int32_t* trace_len) {
@@ -284,6 +319,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
 
   if (o_in) o = *o_in; else or_default_opts(&o);
   if (trace_len) *trace_len = 0;
+  if (alg == OR_ALG_POLY) return solve_poly(family, n, p, u0, abstol, maxiters, &o, u_out);
   r.retcode = OR_RC_MAXITERS; r.iters = 0; r.nfev = 0; r.njev = 0; r.fnorm_inf = INFINITY;
 
   memcpy(u, u0, sizeof(double) * n);

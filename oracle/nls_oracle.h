@@ -17,6 +17,8 @@
  *   NEWTON ................. Sec. 2.1 eq. (newton_descent), L-inf stopping test
  *   NEWTON_ARMIJO .......... Sec. 2.2.1 eq. (sufficient-decrease), backtracking
  *   DOGLEG ................. Sec. 2.2.2 eq. (tr_subproblem), ratio rho_k, Powell dogleg
+ *   POLY ................... Sec. 3.2 default poly-algorithm, first-order part
+ *                            (Newton, then Newton with line search, then trust region)
  */
 #ifndef NLS_ORACLE_H
 #define NLS_ORACLE_H
@@ -28,7 +30,7 @@ extern "C" {
 #endif
 
 enum { OR_FAM_CUBIC = 0, OR_FAM_TANH = 1, OR_FAM_ROSENBROCK = 2, OR_FAM_PAPER = 3 };
-enum { OR_ALG_NEWTON = 0, OR_ALG_ARMIJO = 1, OR_ALG_DOGLEG = 2 };
+enum { OR_ALG_NEWTON = 0, OR_ALG_ARMIJO = 1, OR_ALG_DOGLEG = 2, OR_ALG_POLY = 3 };
 enum {
   OR_RC_SUCCESS = 0, OR_RC_MAXITERS = 1, OR_RC_SINGULAR = 2, OR_RC_NONFINITE = 3,
   OR_RC_LINESEARCH_FAILED = 4, OR_RC_TR_COLLAPSED = 5
@@ -93,7 +95,12 @@ typedef struct {
   double fnorm_inf;
 } or_result;
 
-/* Solve one system.  u_out receives the final iterate.  trace may be NULL. */
+/* Solve one system.  u_out receives the final iterate.  trace may be NULL
+ * (POLY writes no trace).  POLY runs NEWTON, ARMIJO and DOGLEG in that order,
+ * each from u0 with the full iteration budget, and stops at the first
+ * SUCCESS; if none succeeds it returns the attempt with the smallest
+ * ||F||_inf (the earliest on ties).  Its iters, nfev and njev are totals over
+ * the attempts it ran. */
 or_result or_solve_one(int family, int n, int alg, const double* p, const double* u0,
                        double abstol, int32_t maxiters, const or_opts* o, double* u_out,
                        double* trace, int32_t trace_cap, int32_t* trace_len);

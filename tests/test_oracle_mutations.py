@@ -45,6 +45,12 @@ MUTANTS = {
     "radius not shrunk": ("Delta = o.tr_shrink * nstep;", "Delta = nstep;"),
     "predicted reduction sign": ("lin[i] = F[i] + s;", "lin[i] = F[i] - s;"),
     "norm is last component": ("double v = fabs(x[i]); if (v > m) m = v;", "double v = fabs(x[i]); m = v;"),
+    "poly restarts from the failed endpoint": ("r = or_solve_one(family, n, chain[a], p, u0, abstol,",
+                                              "r = or_solve_one(family, n, chain[a], p, a ? u_out : u0, abstol,"),
+    "poly keeps the last attempt": ("if (!have || r.retcode == OR_RC_SUCCESS || r.fnorm_inf < best.fnorm_inf)",
+                                    "if (1)"),
+    "poly counts only the reported attempt": ("  best.iters = iters;\n", "  best.iters = best.iters;\n"),
+    "poly stage order": ("{OR_ALG_NEWTON, OR_ALG_ARMIJO, OR_ALG_DOGLEG}", "{OR_ALG_NEWTON, OR_ALG_DOGLEG, OR_ALG_ARMIJO}"),
     "iteration count off by one": ("r.retcode = OR_RC_SUCCESS; r.iters = k; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)",
                                    "r.retcode = OR_RC_SUCCESS; r.iters = k + 1; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)"),
 }
