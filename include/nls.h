@@ -71,6 +71,13 @@ extern "C" {
 #define NLS_ALG_NEWTON 0        /* Sec. 2.1                                  */
 #define NLS_ALG_NEWTON_ARMIJO 1 /* Sec. 2.2.1, backtracking                  */
 #define NLS_ALG_DOGLEG 2        /* Sec. 2.2.2, trust region + Powell dogleg  */
+/* Sec. 3.2, first-order part of the default poly-algorithm: NEWTON, then
+ * NEWTON_ARMIJO, then DOGLEG, each from u0 with the full maxiters, stopping at
+ * the first SUCCESS; if none succeeds, the attempt with the smallest
+ * ||F||_inf (the earliest on ties) is returned.  u, fnorm_inf and retcode
+ * come from the returned attempt; iters, nfev and njev are totals over the
+ * attempts run.  nls_solve_batch only (the request server refuses it).      */
+#define NLS_ALG_POLY 3
 
 /* ---- precision forms ----------------------------------------------------
  * FP64       : everything in binary64.

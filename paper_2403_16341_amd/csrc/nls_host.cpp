@@ -202,7 +202,7 @@ std::string validate(const nls_batch* b, int64_t* first_bad) {
       std::snprintf(buf, sizeof buf, "system %lld: family %d is not defined at n = %d", (long long)s, fam, n);
       return buf;
     }
-    if (alg < 0 || alg >= ALG_COUNT) {
+    if (alg < 0 || alg >= ALG_KEYS) {
       if (first_bad) *first_bad = s;
       std::snprintf(buf, sizeof buf, "system %lld: unknown algorithm %d", (long long)s, alg);
       return buf;
@@ -271,13 +271,13 @@ Mapping fixed_mapping(int n) {
 
 namespace {
 
-// dense index of an (n, family, algorithm) combination
-constexpr int kCombos = NLS_NMAX * FAM_COUNT * ALG_COUNT;
-inline int combo_index(int n, int fam, int alg) { return ((n - 1) * FAM_COUNT + fam) * ALG_COUNT + alg; }
+// dense index of an (n, family, algorithm) combination (POLY included)
+constexpr int kCombos = NLS_NMAX * FAM_COUNT * ALG_KEYS;
+inline int combo_index(int n, int fam, int alg) { return ((n - 1) * FAM_COUNT + fam) * ALG_KEYS + alg; }
 inline void combo_split(int ci, int* n, int* fam, int* alg) {
-  *alg = ci % ALG_COUNT;
-  *fam = (ci / ALG_COUNT) % FAM_COUNT;
-  *n = ci / (ALG_COUNT * FAM_COUNT) + 1;
+  *alg = ci % ALG_KEYS;
+  *fam = (ci / ALG_KEYS) % FAM_COUNT;
+  *n = ci / (ALG_KEYS * FAM_COUNT) + 1;
 }
 
 struct Launch {
@@ -285,6 +285,15 @@ struct Launch {
   bool lane;
   int key_n, fam, alg;
   double cost;  // estimated work (sum of n^3) for branch balancing
+  bool poly = false;  // the Newton stage of POLY systems
+};
+
+// The Newton-stage launch of a group of POLY systems; its later stages reuse
+// the launch's kernel mapping and system list.
+struct PolySeg {
+  KArgs a;
+  bool lane;
+  int key_n, fam;
 };
 
 struct DevBuf {
@@ -439,6 +448,87 @@ int run_launches(nls_context* c, std::vector<Launch>& L, int prec) {
   return e == hipSuccess ? 0 : -(int)e;
 }
 
+// The fallback chain of Sec. 3.2 for POLY systems, once the Newton stage has
+// written the results: the systems it left unsolved are gathered on the
+// device, solved again from u0 with Newton + Armijo into scratch outputs and
+// folded into the results; those still unsolved get the dogleg stage.  Every
+// step is a kernel on the context's stream and the host never reads a count.
+int run_poly(nls_context* c, const std::vector<PolySeg>& segs, int prec, DevBuf& db, int64_t M, int64_t utotal) {
+  const int ns = (int)segs.size();
+  if (ns == 0) return 0;
+  std::vector<int64_t> at(ns);
+  int64_t lists = 0;
+  for (int k = 0; k < ns; ++k) {
+    at[k] = lists;
+    lists += segs[k].a.count;
+  }
+  const KArgs& r = segs[0].a;  // every segment writes the same result arrays
+  void *sel1, *sel2, *cnt, *ut, *fnt, *itt, *rct, *nft = nullptr, *njt = nullptr;
+  hipError_t e;
+  if ((e = db.alloc(&sel1, lists * 4)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&sel2, lists * 4)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&cnt, (size_t)ns * 4 * 8)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&ut, utotal * 8)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&fnt, M * 8)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&itt, M * 4)) != hipSuccess) return -(int)e;
+  if ((e = db.alloc(&rct, M * 4)) != hipSuccess) return -(int)e;
+  if (r.nfev && (e = db.alloc(&nft, M * 4)) != hipSuccess) return -(int)e;
+  if (r.njev && (e = db.alloc(&njt, M * 4)) != hipSuccess) return -(int)e;
+  // per segment k: cnt[4k + stage] = systems handed to the stage,
+  // cnt[4k + 2 + stage] = that stage's work counter
+  int64_t* const cn = (int64_t*)cnt;
+  if (int z = launch_zero_counters(cn, 4 * ns, c->stream); z < 0) return z;
+  for (int stage = 0; stage < 2; ++stage) {
+    const int alg = stage == 0 ? ALG_ARMIJO : ALG_DOGLEG;
+    int32_t* const out = (int32_t*)(stage == 0 ? sel1 : sel2);
+    for (int k = 0; k < ns; ++k) {
+      const KArgs& g = segs[k].a;
+      const int32_t* in = stage == 0 ? g.sys : (const int32_t*)sel1 + at[k];
+      const int64_t* in_count = stage == 0 ? nullptr : cn + 4 * k;
+      int z = launch_poly_select(in, in_count, g.count, r.retcode, out + at[k], cn + 4 * k + stage, c->stream);
+      if (z < 0) return z;
+    }
+    for (int k = 0; k < ns; ++k) {
+      KArgs a = segs[k].a;
+      a.sys = out + at[k];
+      a.count_dev = cn + 4 * k + stage;
+      a.counter = cn + 4 * k + 2 + stage;
+      a.u_out = (double*)ut;
+      a.fnorm = (double*)fnt;
+      a.iters = (int32_t*)itt;
+      a.retcode = (int32_t*)rct;
+      a.nfev = (int32_t*)nft;
+      a.njev = (int32_t*)njt;
+      int z = launch(segs[k].key_n, segs[k].lane, segs[k].fam, alg, prec, a, c->stream);
+      if (z != 0) return z;
+    }
+    for (int k = 0; k < ns; ++k) {
+      const KArgs& g = segs[k].a;
+      PolyMergeArgs m{};
+      m.list = out + at[k];
+      m.count = cn + 4 * k + stage;
+      m.cap = g.count;
+      m.nsys = g.nsys;
+      m.n = g.n;
+      m.u_off = g.u_off;
+      m.u = r.u_out;
+      m.fnorm = r.fnorm;
+      m.iters = r.iters;
+      m.retcode = r.retcode;
+      m.nfev = r.nfev;
+      m.njev = r.njev;
+      m.u_t = (const double*)ut;
+      m.fnorm_t = (const double*)fnt;
+      m.iters_t = (const int32_t*)itt;
+      m.retcode_t = (const int32_t*)rct;
+      m.nfev_t = (const int32_t*)nft;
+      m.njev_t = (const int32_t*)njt;
+      if (int z = launch_poly_merge(m, c->stream); z < 0) return z;
+    }
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -449,8 +539,9 @@ int nls_nparams(int family, int n) { return nparams_of(family, n); }
 
 int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precision, int32_t* lanes_per_system) {
   if (!c || !lanes_per_system) return fail(nullptr, NLS_E_INVALID, "nls_get_mapping: NULL argument");
-  if (!supported(family, n) || alg < 0 || alg >= ALG_COUNT || (precision != 0 && precision != 1))
+  if (!supported(family, n) || alg < 0 || alg >= ALG_KEYS || (precision != 0 && precision != 1))
     return fail(nullptr, NLS_E_INVALID, "nls_get_mapping: bad combination");
+  if (alg == ALG_POLY) alg = ALG_NEWTON;  // every stage of the chain runs on the Newton stage's mapping
   const int group_l = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
   if (n > 8) { *lanes_per_system = group_l; return NLS_OK; }
   if (family == FAM_PAPER) { *lanes_per_system = 1; return NLS_OK; }
@@ -564,14 +655,16 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   const bool uniform = uniform_batch(b, &fam0, &n0, &alg0);
   const int P0 = nparams_of(fam0, n0);
   // total payload extents
-  int64_t ptotal = 0, utotal = 0;
+  int64_t ptotal = 0, utotal = 0, npoly = 0;
   if (uniform) {
     ptotal = M * (int64_t)P0;
     utotal = M * (int64_t)n0;
+    npoly = alg0 == ALG_POLY ? M : 0;
   } else {
     for (int64_t s = 0; s < M; ++s) {
       const int fam = b->family ? b->family[s] : b->family_all;
       const int n = b->n ? b->n[s] : b->n_all;
+      npoly += (b->alg ? b->alg[s] : b->alg_all) == ALG_POLY;
       const int64_t pe = (b->p_offset ? b->p_offset[s] : ptotal) + nparams_of(fam, n);
       const int64_t ue = (b->u_offset ? b->u_offset[s] : utotal) + n;
       if (b->p_offset) ptotal = std::max(ptotal, pe); else ptotal = pe;
@@ -587,6 +680,8 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   uint64_t need = 0;
   if (!dev) need += (uint64_t)(ptotal + 2 * utotal + M) * 8 + (uint64_t)M * 16;
   if (!uniform) need += (uint64_t)M * (4 + 1 + 16) + 16;
+  // the chain's lists, counts and scratch outputs
+  if (npoly) need += (uint64_t)npoly * 8 + (uint64_t)utotal * 8 + (uint64_t)M * 24 + 4 * 8 * kCombos;
   if (c->budget && c->held_bytes + need > c->budget) {
     if (need > c->budget) return fail(c, NLS_E_NOMEM, "batch needs more device memory than the budget");
     return fail(c, NLS_E_NOMEM, "budget exhausted by outstanding tickets; query them first");
@@ -659,7 +754,8 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   base.o = to_kopts(opts);
 
   if (M > 0 && uniform) {
-    const Mapping mp = choose_mapping(c, n0, fam0, alg0, b->precision, base, P0, M, nullptr, nullptr);
+    const int alg1 = alg0 == ALG_POLY ? ALG_NEWTON : alg0;  // the chain starts with Newton
+    const Mapping mp = choose_mapping(c, n0, fam0, alg1, b->precision, base, P0, M, nullptr, nullptr);
     if (mp.error) return bail(mp.error, "autotune");
     if (int z = launch_zero_counters(c->counters, 1, c->stream); z < 0) return bail((hipError_t)(-z), "zero counters");
     KArgs a = base;
@@ -667,9 +763,15 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     a.P = P0;
     a.n = n0;
     a.counter = c->counters;
-    int rcode = launch(mp.key_n, mp.lane, fam0, alg0, b->precision, a, c->stream);
+    int rcode = launch(mp.key_n, mp.lane, fam0, alg1, b->precision, a, c->stream);
     if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
     if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
+    if (alg0 == ALG_POLY) {
+      std::vector<PolySeg> segs{PolySeg{a, mp.lane, mp.key_n, fam0}};
+      rcode = run_poly(c, segs, b->precision, db, M, utotal);
+      if (rcode < 0) return bail((hipError_t)(-rcode), "fallback chain");
+      if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
+    }
   } else if (M > 0) {
     // Bucket by kernel: counting sort of the systems on a dense key
     // (mapping, size bucket, family, algorithm), one persistent launch per
@@ -731,9 +833,11 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       a.nsys = (const uint8_t*)dn;
       a.count = c1 - c0;
       a.P = 0;
-      const Mapping mp = choose_mapping(c, n, fam, alg, b->precision, a, 0, c1 - c0, a.sys, a.p_off);
+      const bool poly = alg == ALG_POLY;
+      const int alg1 = poly ? ALG_NEWTON : alg;  // the chain starts with Newton
+      const Mapping mp = choose_mapping(c, n, fam, alg1, b->precision, a, 0, c1 - c0, a.sys, a.p_off);
       if (mp.error) return bail(mp.error, "autotune");
-      const int kid = (mp.lane ? 0 : 1000) + mp.key_n * 16 + fam * 4 + alg;
+      const int kid = (mp.lane ? 0 : 1000) + mp.key_n * 16 + fam * ALG_KEYS + alg;
       auto it = by_kernel.find(kid);
       if (it != by_kernel.end() && !mp.lane && launches[it->second].a.sys + launches[it->second].a.count == a.sys) {
         launches[it->second].a.count += a.count;  // adjacent in the sorted order
@@ -741,7 +845,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
         continue;
       }
       a.n = mp.key_n;
-      Launch L{a, mp.lane, mp.key_n, fam, alg, (double)a.count * n * n * n};
+      Launch L{a, mp.lane, mp.key_n, fam, alg1, (double)a.count * n * n * n, poly};
       by_kernel[kid] = launches.size();
       launches.push_back(L);
     }
@@ -749,6 +853,12 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     for (size_t i = 0; i < launches.size(); ++i) launches[i].a.counter = c->counters + i;
     int rcode = run_launches(c, launches, b->precision);
     if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
+    if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
+    std::vector<PolySeg> segs;
+    for (auto& x : launches)
+      if (x.poly) segs.push_back(PolySeg{x.a, x.lane, x.key_n, x.fam});
+    rcode = run_poly(c, segs, b->precision, db, M, utotal);
+    if (rcode < 0) return bail((hipError_t)(-rcode), "fallback chain");
     if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
   }
 

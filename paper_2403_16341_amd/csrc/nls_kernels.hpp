@@ -362,6 +362,13 @@ __device__ __forceinline__ int64_t trip_limit(int32_t maxit, int32_t mh) {
   return (int64_t)maxit * ((int64_t)(mh > 0 ? mh : 0) + 1) + 4;
 }
 
+// slots of a launch: count, or the device-side count when one is given
+__device__ __forceinline__ int64_t launch_slots(const KArgs& a) {
+  if (!a.count_dev) return a.count;
+  const int64_t c = *a.count_dev;
+  return c < a.count ? (c > 0 ? c : 0) : a.count;
+}
+
 // Chunk staging.  Lane l copies the P parameters and the N starting values of
 // system l of the chunk from global memory into LDS "column" l: a region of
 // K doubles is laid out as 16-byte granules (granule g of lane l at byte
@@ -440,7 +447,8 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   const bool staged = P > 0 && a.sys == nullptr && a.p_off == nullptr && a.u_off == nullptr &&
                       (!StageRegion<PS>::X4 || (reinterpret_cast<uintptr_t>(a.params) & 15) == 0) &&
                       (!StageRegion<N>::X4 || (reinterpret_cast<uintptr_t>(a.u0) & 15) == 0);
-  const int64_t nchunks = (a.count + 63) / 64;
+  const int64_t count = launch_slots(a);
+  const int64_t nchunks = (count + 63) / 64;
   const double tol = a.abstol;
   const int32_t maxit = a.maxiters;
   const double c2 = 2.0 * a.o.armijo_c;
@@ -461,7 +469,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   int buf_next = 0, buf_cnt = 0;
   bool buf_wait = false;
   if (chunk < nchunks) {
-    buf_cnt = (int)min<int64_t>(64, a.count - chunk * 64);
+    buf_cnt = (int)min<int64_t>(64, count - chunk * 64);
     if (staged) {
       stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
       buf_wait = true;
@@ -534,7 +542,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         wave_sync();
         chunk = next_chunk(chunk);
         buf_next = 0;
-        buf_cnt = chunk < nchunks ? (int)min<int64_t>(64, a.count - chunk * 64) : 0;
+        buf_cnt = chunk < nchunks ? (int)min<int64_t>(64, count - chunk * 64) : 0;
         if (staged && chunk < nchunks) {
           stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
           buf_wait = true;
@@ -1111,6 +1119,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
   const int64_t total_groups = (int64_t)gridDim.x * G;
   int64_t next_static = (int64_t)blockIdx.x * G + gi;
   const int64_t trip_cap = trip_limit(maxit, mh);
+  const int64_t count = launch_slots(a);
 
   // per-group state (every lane of a group holds the same copy)
   int gst = ST_IDLE;
@@ -1171,7 +1180,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
         t = next_static;
         next_static += total_groups;
       }
-      if (t >= a.count) {
+      if (t >= count) {
         exhausted = true;
       } else {
         s = a.sys ? (int64_t)a.sys[t] : t;

@@ -24,6 +24,36 @@ NLS_DECL_GROUPS(f32)
 // zero `count` work counters on the stream
 int launch_zero_counters(int64_t* c, int count, hipStream_t st);
 
+// Fallback chain steps.  select: out <- the listed systems (in[j], j <
+// min(*in_count, cap); in null = 0..cap-1, in_count null = cap) whose retcode
+// is neither SUCCESS nor INVALID, *out_count (zeroed before) <- their number.
+int launch_poly_select(const int32_t* in, const int64_t* in_count, int64_t cap, const int32_t* rc, int32_t* out,
+                       int64_t* out_count, hipStream_t st);
+
+// merge: for the systems list[j], j < min(*count, cap), fold the attempt in
+// the *_t arrays into the results (see k_poly_merge).
+struct PolyMergeArgs {
+  const int32_t* list;
+  const int64_t* count;
+  int64_t cap;
+  const uint8_t* nsys;  // per-system n, or null with n uniform
+  int32_t n;
+  const int64_t* u_off;  // null: system s at s * n
+  double* u;
+  double* fnorm;
+  int32_t* iters;
+  int32_t* retcode;
+  int32_t* nfev;  // may be null
+  int32_t* njev;  // may be null
+  const double* u_t;
+  const double* fnorm_t;
+  const int32_t* iters_t;
+  const int32_t* retcode_t;
+  const int32_t* nfev_t;
+  const int32_t* njev_t;
+};
+int launch_poly_merge(const PolyMergeArgs& a, hipStream_t st);
+
 // dispatch over the buckets 16, 24, ..., 64
 inline int launch_group(int prec, int nb, int fam, int alg, const KArgs& a, hipStream_t st) {
 #define NLS_CASE(NB) \

@@ -388,6 +388,7 @@ int nls_server_submit(nls_server* s, const nls_batch* b, const nls_results* r, u
     if ((b->family && b->family[i] != q.fam) || (b->n && b->n[i] != q.n) || (b->alg && b->alg[i] != q.alg))
       return sfail(NLS_E_INVALID, "server requests have one family, size and algorithm");
   }
+  if (q.alg == ALG_POLY) return sfail(NLS_E_INVALID, "the fallback chain runs through nls_solve_batch only");
   q.P = nparams_of(q.fam, q.n);
   q.key = merge_key(q);
   std::lock_guard<std::mutex> lk(s->mu);

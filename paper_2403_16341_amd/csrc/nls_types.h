@@ -7,6 +7,9 @@ namespace nls {
 
 enum : int { FAM_CUBIC = 0, FAM_TANH = 1, FAM_ROSENBROCK = 2, FAM_PAPER = 3, FAM_COUNT = 4 };
 enum : int { ALG_NEWTON = 0, ALG_ARMIJO = 1, ALG_DOGLEG = 2, ALG_COUNT = 3 };
+// the fallback chain NEWTON -> ARMIJO -> DOGLEG, run by the host runtime as
+// three stages of the kernels above (no kernel of its own)
+enum : int { ALG_POLY = 3, ALG_KEYS = 4 };
 enum : int { PREC_FP64 = 0, PREC_FP32_INNER = 1 };
 enum : int {
   RC_SUCCESS = 0,
@@ -37,8 +40,9 @@ struct KOpts {
   }
 };
 
-// Arguments of one solver launch.  The launch handles `count` slots; slot t
-// solves system sys[t] (or t when sys is null).  Parameters of system s start
+// Arguments of one solver launch.  The launch handles `count` slots, or
+// min(*count_dev, count) when count_dev is set (a count produced on the device
+// by an earlier kernel); slot t solves system sys[t] (or t when sys is null).  Parameters of system s start
 // at params + p_off[s] (or s * P), its unknowns at u0 + u_off[s] (or s * n).
 struct KArgs {
   const double* params;
@@ -54,6 +58,7 @@ struct KArgs {
   const int32_t* sys;
   const uint8_t* nsys;  // per-system n (group mapping, mixed sizes); may be null
   int64_t* counter;     // dynamic work counter (zeroed before the launch); may be null
+  const int64_t* count_dev;  // may be null
   int64_t count;
   int64_t P;
   int32_t n;            // uniform n when nsys is null

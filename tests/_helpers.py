@@ -56,6 +56,33 @@ def _same(b, x, y, s):
     return e <= (REL if x["retcode"][s] == oracle.RC_SUCCESS else 1e-6)
 
 
+def _poly_attempts_sensitive(b, o, opts):
+    """A POLY system's outcome is decided by its attempts: whether a stage
+    succeeds decides whether the next one runs, and when all fail the smallest
+    residual picks the result.  So the system is rounding-sensitive when any
+    attempt the chain makes is (a Newton trajectory stalled at its cap can
+    wander anywhere, and may as well land on a root), under the same probes as
+    the chain itself."""
+    out = np.zeros(b.M, dtype=bool)
+    idx = np.nonzero(b.alg == oracle.POLY)[0]
+    if idx.size == 0:
+        return out
+    sub = b.subset(idx)
+    up, dn = np.nextafter(sub.u0, np.inf), np.nextafter(sub.u0, -np.inf)
+    running = np.ones(sub.M, dtype=bool)  # the chain reaches this stage
+    for alg in (oracle.NEWTON, oracle.ARMIJO, oracle.DOGLEG):
+        sub.alg[:] = alg
+        base = run_oracle(sub, opts)
+        probes = [run_oracle(sub, opts, variant="fma"), run_oracle(sub, opts, u0=up),
+                  run_oracle(sub, opts, u0=dn), run_oracle(sub, opts, variant="fma", u0=up),
+                  run_oracle(sub, opts, variant="fma", u0=dn)]
+        for j in np.nonzero(running)[0]:
+            if not all(_same(sub, base, q, j) for q in probes):
+                out[idx[j]] = True
+        running &= base["retcode"] != oracle.RC_SUCCESS
+    return out
+
+
 def classify(b, g, opts=None, strict_all=False, u_tol="strict"):
     """Compare GPU results g with the oracle.
 
@@ -77,6 +104,7 @@ def classify(b, g, opts=None, strict_all=False, u_tol="strict"):
               run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn)]
     M = b.M
     sens = np.array([not all(_same(b, o, q, s) for q in probes) for s in range(M)], dtype=bool)
+    sens |= _poly_attempts_sensitive(b, o, opts)
     if strict_all:
         sens[:] = False
     report = dict(M=M, sensitive=int(sens.sum()), success_gpu=int((g["retcode"] == 0).sum()),

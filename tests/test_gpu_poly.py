@@ -1,0 +1,208 @@
+"""GPU parity of the fallback chain (POLY, Sec. 3.2): Newton, then Newton with
+the Armijo line search, then the dogleg trust region, each from u0.  Same bar
+as the single algorithms: identical return codes, iteration totals within
++-1, relative u error <= 1e-9 on systems both sides solve (rounding-sensitive
+systems classified as in the other parity tests)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_16341_amd import inputs
+
+from _helpers import classify, np_residual, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nls():
+    from paper_2403_16341_amd import nls as _nls
+    _nls.lib()
+    return _nls
+
+
+@pytest.fixture(scope="module")
+def ctx(nls):
+    c = nls.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(nls, ctx, b, precision=None):
+    return nls.results_to_numpy(ctx.solve(nls.DeviceBatch(b), precision=precision))
+
+
+def compare(b, g, label, max_other_root=0, u_tol="strict"):
+    rep, o = classify(b, g, u_tol=u_tol)
+    rep["label"] = label
+    print({k: (v[:5] if isinstance(v, list) else v) for k, v in rep.items()}, flush=True)
+    assert not rep["strict_fail"], (label, rep["strict_fail"][:5])
+    assert rep["other_root"] <= max_other_root, (label, rep["other_root"])
+    assert (g["retcode"] != 6).all(), label  # no system marked invalid on the device
+    # every reported residual norm is that of the returned point, whichever
+    # attempt it came from
+    for s in range(b.M):
+        fn = g["fnorm_inf"][s]
+        if np.isfinite(fn):
+            f_, n_, _, p_, _ = b.system(s)
+            F = np_residual(f_, p_, g["u"][b.u_off[s]:b.u_off[s] + n_])
+            assert abs(np.abs(F).max() - fn) <= 1e-12 + 1e-9 * fn, (label, s)
+    return rep, o
+
+
+def _stages_used(b):
+    """How many systems the oracle's chain ended in stage 1, 2 and 3 (from
+    the single-algorithm oracle runs on the same inputs)."""
+    used = [0, 0, 0]
+    prev_fail = np.ones(b.M, bool)
+    for k, alg in enumerate((oracle.NEWTON, oracle.ARMIJO, oracle.DOGLEG)):
+        r = oracle.solve_batch(b.family, b.n, np.full(b.M, alg, np.uint8), b.params, b.p_off, b.u0,
+                               b.u_off, b.abstol, b.maxiters, nthreads=8)
+        ok = r["retcode"] == oracle.RC_SUCCESS
+        used[k] = int((prev_fail & ok).sum())
+        prev_fail &= ~ok
+    return used
+
+
+@pytest.mark.parametrize("fam", [inputs.CUBIC, inputs.TANH])
+@pytest.mark.parametrize("n", [1, 3, 8, 9, 16, 24, 40, 64])
+def test_poly_grid(nls, ctx, fam, n):
+    """Every mapping (lane n <= 8, 16/32/64-lane groups), starts far enough
+    out that all three stages are needed on part of the batch."""
+    rng = np.random.Generator(np.random.PCG64(5000 + 10 * n + fam))
+    M = 70 if n <= 16 else 23
+    if fam == inputs.CUBIC:
+        p, u0 = inputs.cubic_params(rng, M, n), rng.uniform(-6, 6, (M, n))
+    else:
+        p, u0 = inputs.tanh_params(rng, M, n), rng.uniform(-4, 4, (M, n))
+    b = inputs.homogeneous(fam, n, inputs.POLY, p, u0, 1e-10, 25)
+    print("case: poly fam=%d n=%d" % (fam, n), flush=True)
+    g = run_gpu(nls, ctx, b)
+    compare(b, g, "poly-grid", max_other_root=0 if fam == inputs.CUBIC else M // 10)
+
+
+def test_poly_reaches_later_stages(nls, ctx):
+    """A tanh batch on which the chain ends in each of its three stages."""
+    b = inputs.config(3, M=64 * 6 + 11)
+    b.alg[:] = inputs.POLY
+    b.maxiters = 40
+    g = run_gpu(nls, ctx, b)
+    rep, o = compare(b, g, "poly-tanh16", max_other_root=b.M // 50)
+    # most systems are held to the strict bar (the rest have an attempt that
+    # rounding can steer, e.g. Newton wandering at its cap)
+    assert rep["sensitive"] <= b.M // 5
+    used = _stages_used(b)
+    print("chain ended in stage 1/2/3:", used, flush=True)
+    assert min(used) > 0
+    # the chain solves at least what each stage solves alone
+    assert rep["success_gpu"] >= max(used[0], sum(used) - rep["sensitive"])
+
+
+def test_poly_in_mixed_batch(nls, ctx):
+    """POLY systems interleaved with single-algorithm systems of every size:
+    several Newton-stage launches (lane and group, merged buckets), each with
+    its own device-side lists for the later stages."""
+    b = inputs.config(4, M=1500)
+    rng = np.random.Generator(np.random.PCG64(91))
+    b.alg[rng.random(b.M) < 0.5] = inputs.POLY
+    g = run_gpu(nls, ctx, b)
+    compare(b, g, "poly-mixed", max_other_root=b.M // 50)
+    # the single-algorithm systems are unchanged by their POLY neighbours
+    keep = b.alg != inputs.POLY
+    sub = b.subset(np.nonzero(keep)[0])
+    gs = run_gpu(nls, ctx, sub)
+    idx = np.nonzero(keep)[0]
+    for key in ("iters", "retcode", "fnorm_inf", "nfev", "njev"):
+        assert np.array_equal(g[key][idx], gs[key], equal_nan=True), key
+    gu = np.concatenate([g["u"][b.u_off[s]:b.u_off[s + 1]] for s in idx])
+    assert np.array_equal(gu, gs["u"])
+
+
+def test_poly_host_device_and_repeat_bitwise(nls, ctx):
+    b = inputs.config(4, M=700)
+    b.alg[:] = inputs.POLY
+    g1 = run_gpu(nls, ctx, b)
+    g2 = run_gpu(nls, ctx, b)
+    h = nls.solve_host(ctx, b)
+    for key in ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev"):
+        assert np.array_equal(g1[key], g2[key], equal_nan=True), key
+        assert np.array_equal(g1[key], h[key], equal_nan=True), key
+
+
+def test_poly_edge_cases(nls, ctx):
+    cases = [
+        inputs.rosenbrock(7, 10, seed=7, alg=inputs.POLY, u0="paper"),
+        inputs.rosenbrock(100, 8, seed=6, alg=inputs.POLY),
+        inputs.paper_example(64, seed=8, alg=inputs.POLY),
+        inputs.singular_cubic(5, 3, alg=inputs.POLY),
+        inputs.singular_cubic(5, 12, alg=inputs.POLY),
+        inputs.no_root_tanh(20, 5, seed=10, alg=inputs.POLY),
+        inputs.no_root_tanh(20, 11, seed=11, alg=inputs.POLY),
+    ]
+    for b in cases:
+        print("case: poly", b.name, b.M, int(b.n[0]), flush=True)
+        g = run_gpu(nls, ctx, b)
+        compare(b, g, "poly-" + b.name, u_tol="bound" if b.name in ("rosenbrock", "paper-example") else "strict")
+        if b.name == "rosenbrock" and int(b.n[0]) == 10:
+            # only the trust-region stage converges from the paper's start
+            assert (g["retcode"] == oracle.RC_SUCCESS).all()
+            assert np.abs(g["u"] - 1.0).max() <= 1e-8
+        if b.name == "singular-cubic":
+            assert (g["retcode"] == oracle.RC_SINGULAR).all() and (g["iters"] == 3).all()
+            assert (g["njev"] == 3).all() and (g["nfev"] == 3).all()
+        if b.name == "no-root-tanh":
+            assert (g["retcode"] != oracle.RC_SUCCESS).all()
+    # non-finite starts and a zero budget: every stage gives up at its start
+    b = inputs.config(2, M=130)
+    b.alg[:] = inputs.POLY
+    b.u0[8 * 3 + 2] = np.nan
+    b.params[72 * 5 + 10] = np.inf
+    g = run_gpu(nls, ctx, b)
+    compare(b, g, "poly-nonfinite")
+    assert g["retcode"][3] == oracle.RC_NONFINITE and g["iters"][3] == 0 and g["nfev"][3] == 3
+    assert g["retcode"][5] == oracle.RC_NONFINITE
+    b0 = inputs.config(1, M=100)
+    b0.alg[:] = inputs.POLY
+    b0.maxiters = 0
+    g = run_gpu(nls, ctx, b0)
+    assert (g["retcode"] == oracle.RC_MAXITERS).all() and (g["iters"] == 0).all() and (g["nfev"] == 3).all()
+    assert np.array_equal(g["u"], b0.u0)
+
+
+def test_poly_fp32_inner(nls, ctx):
+    """FP32-inner chain on the mixed workload: every success passes the FP64
+    stopping test and the cubic systems reach the FP64 oracle's root."""
+    b = inputs.config(4, M=1200)
+    b.alg[:] = inputs.POLY
+    g = run_gpu(nls, ctx, b, precision=inputs.PREC_FP32_INNER)
+    o = run_oracle(b)
+    assert (g["retcode"] != nls.RC_INVALID).all()
+    succ = g["retcode"] == oracle.RC_SUCCESS
+    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+    cub = b.family == inputs.CUBIC
+    both = succ & (o["retcode"] == oracle.RC_SUCCESS) & cub
+    assert both.sum() >= 0.95 * cub.sum()
+    for s in np.nonzero(both)[0]:
+        sl = slice(b.u_off[s], b.u_off[s + 1])
+        assert np.abs(g["u"][sl] - o["u"][sl]).max() <= 1e-8 * max(1.0, np.abs(o["u"][sl]).max())
+
+
+def test_poly_full_size_sampled(nls, ctx):
+    """The 262,144 x N=16 tanh workload under the chain, in the launch the
+    benchmark times: sampled systems against the oracle one by one."""
+    b = inputs.config(3)
+    b.alg[:] = inputs.POLY
+    g = run_gpu(nls, ctx, b)
+    assert (g["retcode"] != nls.RC_INVALID).all()
+    succ = g["retcode"] == oracle.RC_SUCCESS
+    assert (g["fnorm_inf"][succ] <= b.abstol).all()
+    rng = np.random.Generator(np.random.PCG64(78))
+    idx = np.sort(rng.choice(b.M, 400, replace=False))
+    sub = b.subset(idx)
+    gs = {k: (v[idx] if k != "u" else np.concatenate([v[b.u_off[s]:b.u_off[s + 1]] for s in idx]))
+          for k, v in g.items() if isinstance(v, np.ndarray)}
+    # with 100 iterations a Newton attempt that wanders at first can still
+    # land on a root, and tanh systems have several: where rounding steers
+    # that, both sides may end on different valid roots
+    rep, _ = compare(sub, gs, "poly-tanh16-sampled", max_other_root=len(idx) // 20)
+    assert rep["sensitive"] <= len(idx) // 5
