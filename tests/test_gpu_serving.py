@@ -150,7 +150,7 @@ def test_server_offsets_empty_and_refusals(nls, requests):
         assert np.array_equal(g[k], r[k])
 
     # refusals: larger than the whole budget, several sizes in one request,
-    # a size outside 1..64
+    # a size outside 1..64, the fallback chain
     small = nls.Server(0, mem_budget_bytes=1 << 16)
     big = inputs.homogeneous(inputs.CUBIC, 8, inputs.ARMIJO, np.zeros((2000, 72)), np.zeros((2000, 8)),
                              1e-10, 10)
@@ -165,6 +165,11 @@ def test_server_offsets_empty_and_refusals(nls, requests):
     c70 = inputs.homogeneous(inputs.CUBIC, 70, inputs.ARMIJO, np.zeros((2, 70 * 71)), np.zeros((2, 70)), 1e-10, 10)
     with pytest.raises(nls.NLSError) as ei:
         srv.submit(c70)
+    assert ei.value.code == nls.E_INVALID
+    # the fallback chain runs through the batch path only
+    chain = inputs.homogeneous(inputs.CUBIC, 4, inputs.POLY, np.zeros((2, 20)), np.zeros((2, 4)), 1e-10, 10)
+    with pytest.raises(nls.NLSError) as ei:
+        srv.submit(chain)
     assert ei.value.code == nls.E_INVALID
     srv.close()
 
