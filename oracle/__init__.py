@@ -9,7 +9,9 @@ GPU path computes, written from the paper (arXiv 2403.16341):
 * Newton-Raphson (Sec. 2.1), Armijo backtracking (Sec. 2.2.1), Powell dogleg
   trust region (Sec. 2.2.2),
 * the first-order part of the default poly-algorithm (Sec. 3.2): the three
-  methods above in turn, each from the starting point, until one succeeds.
+  methods above in turn, each from the starting point, until one succeeds,
+* sensitivities at a solution by the implicit function theorem (Sec. 2.3),
+  tangent and adjoint forms.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
 leg may import this package.  It shares no code with the HIP library.
@@ -112,6 +114,11 @@ def lib(variant: str = "plain"):
                                       ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Opts), P,
                                       P, ctypes.c_int32, P]
         _lib.or_solve_one.restype = _Result
+        _lib.or_param_jacobian.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib.or_tangent.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P]
+        _lib.or_tangent.restype = ctypes.c_int
+        _lib.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        _lib.or_adjoint.restype = ctypes.c_int
         _lib.or_solve_batch.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_double,
                                         ctypes.c_int32, ctypes.POINTER(_Opts), P, P, P, P, P, P,
                                         ctypes.c_int32]
@@ -162,6 +169,36 @@ def jacobian(family: int, p, u) -> np.ndarray:
     J = np.empty((u.size, u.size))
     lib().or_jacobian(family, u.size, _ptr(p), _ptr(u), _ptr(J))
     return J
+
+
+def param_jacobian(family: int, p, u) -> np.ndarray:
+    """dF/dtheta (n x P) at (u, theta), from forward-mode duals on the parameters."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    Jp = np.empty((u.size, max(p.size, 0)))
+    lib().or_param_jacobian(family, u.size, _ptr(p), _ptr(u), _ptr(Jp) if Jp.size else None)
+    return Jp
+
+
+def tangent(family: int, p, u, v):
+    """(rc, du): du = -J^{-1} (dF/dtheta) v at the solution u (Sec. 2.3)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    du = np.empty_like(u)
+    rc = lib().or_tangent(family, u.size, _ptr(p), _ptr(u), _ptr(v), _ptr(du))
+    return rc, du
+
+
+def adjoint(family: int, p, u, w):
+    """(rc, lambda, grad): lambda = J^{-T} w, grad = -(dF/dtheta)^T lambda (Sec. 2.3)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    lam = np.empty_like(u)
+    grad = np.empty_like(p)
+    rc = lib().or_adjoint(family, u.size, _ptr(p), _ptr(u), _ptr(w), _ptr(lam), _ptr(grad))
+    return rc, lam, grad
 
 
 def lu(a):

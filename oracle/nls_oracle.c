@@ -170,6 +170,63 @@ void or_jacobian(int family, int n, const double* p, const double* u, double* J)
   }
 }
 
+/* The residual again, now with dual parameters and a plain u: the tangent  */
+/* part is dF/dtheta along the parameters' seeds.                            */
+static void residual_dual_params(int family, int n, const dual* p, const double* u, dual* F) {
+  int i, j;
+  switch (family) {
+    case OR_FAM_CUBIC: {
+      const dual* A = p;
+      const dual* b = p + n * n;
+      for (i = 0; i < n; ++i) {
+        dual s = dconst(0.0);
+        for (j = 0; j < n; ++j) s = dadd(s, dmul(A[i * n + j], dconst(u[j])));
+        dual cube = dconst(u[i] * u[i] * u[i]);
+        F[i] = dsub(dadd(s, dmul(dconst(0.1), cube)), b[i]);
+      }
+      break;
+    }
+    case OR_FAM_TANH: {
+      const dual* A = p;
+      const dual* b = p + n * n;
+      dual beta = p[n * n + n];
+      for (i = 0; i < n; ++i) {
+        dual s = dconst(0.0);
+        for (j = 0; j < n; ++j) s = dadd(s, dmul(A[i * n + j], dconst(tanh(u[j]))));
+        F[i] = dsub(dadd(s, dmul(beta, dconst(u[i]))), b[i]);
+      }
+      break;
+    }
+    case OR_FAM_ROSENBROCK: {
+      F[0] = dconst(1.0 - u[0]);
+      for (i = 1; i < n; ++i) F[i] = dconst(10.0 * (u[i] - u[i - 1] * u[i - 1]));
+      break;
+    }
+    case OR_FAM_PAPER: {
+      dual a = p[0], b = p[1], c = p[2];
+      dual cube = dconst(u[1] * u[1] * u[1]);
+      F[0] = dadd(dmul(dadd(dconst(u[0]), a), dsub(cube, b)), c);
+      F[1] = dconst(sin(u[1] * exp(u[0]) - 1.0));
+      break;
+    }
+    default:
+      for (i = 0; i < n; ++i) F[i] = dl(NAN, NAN);
+  }
+}
+
+void or_param_jacobian(int family, int n, const double* p, const double* u, double* Jp) {
+  const int P = or_nparams(family, n);
+  dual* pd = (dual*)malloc(sizeof(dual) * (P > 0 ? P : 1));
+  dual Fd[OR_NMAX];
+  int i, j;
+  for (j = 0; j < P; ++j) {
+    for (i = 0; i < P; ++i) pd[i] = dl(p[i], i == j ? 1.0 : 0.0);
+    residual_dual_params(family, n, pd, u, Fd);
+    for (i = 0; i < n; ++i) Jp[i * P + j] = Fd[i].d;
+  }
+  free(pd);
+}
+
 /* ------------------------------------------------------------------------ */
 /* LU with partial pivoting.  Step k: the pivot is the first row (in current */
 /* row order, scanning upward from k) whose |a_ik| is strictly larger than   */
@@ -268,6 +325,74 @@ static int newton_direction(int family, int n, const double* p, const double* u,
   for (i = 0; i < n; ++i) delta[i] = -F[i];
   or_lu_solve(n, lu, piv, delta);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sensitivities at a solution (Sec. 2.3).  Differentiating F(u*(theta),     */
+/* theta) = 0 gives J D + dF/dtheta = 0 with D the derivative of u* in theta */
+/* (implicit function theorem), so D = -J^{-1} dF/dtheta.  The tangent form  */
+/* applies D to one parameter direction v; the adjoint form gives w^T D, the */
+/* gradient of w^T u* with respect to theta, from one solve with J^T.        */
+/* ------------------------------------------------------------------------ */
+static int sens_setup(int family, int n, const double* p, const double* u, double* J, double* Jp, int P) {
+  int i;
+  for (i = 0; i < n; ++i) if (!isfinite(u[i])) return 3;
+  for (i = 0; i < P; ++i) if (!isfinite(p[i])) return 3;
+  or_jacobian(family, n, p, u, J);
+  for (i = 0; i < n * n; ++i) if (!isfinite(J[i])) return 3;
+  if (P > 0) or_param_jacobian(family, n, p, u, Jp);
+  return 0;
+}
+
+int or_tangent(int family, int n, const double* p, const double* u, const double* v, double* du) {
+  const int P = or_nparams(family, n);
+  double J[OR_NMAX * OR_NMAX];
+  double* Jp = (double*)malloc(sizeof(double) * (size_t)n * (P > 0 ? P : 1));
+  int32_t piv[OR_NMAX];
+  int i, j, rc = sens_setup(family, n, p, u, J, Jp, P);
+  if (rc == 0) {
+    /* right-hand side -(dF/dtheta) v */
+    for (i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (j = 0; j < P; ++j) s = s + Jp[i * P + j] * v[j];
+      du[i] = -s;
+    }
+    if (or_lu(n, J, piv) != 0) rc = 2;
+    else or_lu_solve(n, J, piv, du);
+  }
+  if (rc != 0) for (i = 0; i < n; ++i) du[i] = NAN;
+  free(Jp);
+  return rc;
+}
+
+int or_adjoint(int family, int n, const double* p, const double* u, const double* w, double* lambda,
+               double* grad) {
+  const int P = or_nparams(family, n);
+  double J[OR_NMAX * OR_NMAX], Jt[OR_NMAX * OR_NMAX];
+  double* Jp = (double*)malloc(sizeof(double) * (size_t)n * (P > 0 ? P : 1));
+  int32_t piv[OR_NMAX];
+  int i, j, rc = sens_setup(family, n, p, u, J, Jp, P);
+  if (rc == 0) {
+    /* J^T lambda = w, by LU with partial pivoting of the transposed matrix */
+    for (i = 0; i < n; ++i)
+      for (j = 0; j < n; ++j) Jt[i * n + j] = J[j * n + i];
+    for (i = 0; i < n; ++i) lambda[i] = w[i];
+    if (or_lu(n, Jt, piv) != 0) rc = 2;
+    else or_lu_solve(n, Jt, piv, lambda);
+  }
+  if (rc == 0) {
+    /* grad_j = -sum_i lambda_i dF_i/dtheta_j */
+    for (j = 0; j < P; ++j) {
+      double s = 0.0;
+      for (i = 0; i < n; ++i) s = s + lambda[i] * Jp[i * P + j];
+      grad[j] = -s;
+    }
+  } else {
+    for (i = 0; i < n; ++i) lambda[i] = NAN;
+    for (j = 0; j < P; ++j) grad[j] = NAN;
+  }
+  free(Jp);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -19,6 +19,7 @@
  *   DOGLEG ................. Sec. 2.2.2 eq. (tr_subproblem), ratio rho_k, Powell dogleg
  *   POLY ................... Sec. 3.2 default poly-algorithm, first-order part
  *                            (Newton, then Newton with line search, then trust region)
+ *   sensitivities .......... Sec. 2.3, implicit function theorem (tangent and adjoint)
  */
 #ifndef NLS_ORACLE_H
 #define NLS_ORACLE_H
@@ -104,6 +105,22 @@ typedef struct {
 or_result or_solve_one(int family, int n, int alg, const double* p, const double* u0,
                        double abstol, int32_t maxiters, const or_opts* o, double* u_out,
                        double* trace, int32_t trace_cap, int32_t* trace_len);
+
+/* Derivative of F with respect to the parameters, n x P row-major:
+ * Jp[i*P+j] = dF_i/dtheta_j, from P forward-mode JVPs (seed theta_j + eps). */
+void or_param_jacobian(int family, int n, const double* p, const double* u, double* Jp);
+
+/* Sensitivities at a solution u* of F(u, theta) = 0 (Sec. 2.3, implicit
+ * function theorem; J = dF/du at u* must be nonsingular; the minus sign is
+ * the theorem's):
+ *   or_tangent: du = -J^{-1} (dF/dtheta) v     (v: P values; du: n values)
+ *   or_adjoint: lambda = J^{-T} w, grad = -(dF/dtheta)^T lambda
+ *               (w: n values; lambda: n values; grad: P values)
+ * Return 0, 2 (a zero or non-finite pivot in the LU) or 3 (a non-finite
+ * input or Jacobian entry); on a nonzero return the outputs are NaN. */
+int or_tangent(int family, int n, const double* p, const double* u, const double* v, double* du);
+int or_adjoint(int family, int n, const double* p, const double* u, const double* w, double* lambda,
+               double* grad);
 
 /* Solve a batch; offsets are [M+1] prefix arrays.  nthreads >= 1 threads each
  * run or_solve_one over a contiguous chunk.  nfev/njev may be NULL. */

@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nls_oracle.c")
 PINS = ["tests/test_oracle_residual_jacobian.py", "tests/test_oracle_lu.py",
-        "tests/test_oracle_solvers.py"]
+        "tests/test_oracle_solvers.py", "tests/test_oracle_sensitivity.py"]
 
 MUTANTS = {
     "cubic coefficient": ("F[i] = (s + 0.1 * cube) - b[i];", "F[i] = (s + 0.2 * cube) - b[i];"),
@@ -51,6 +51,14 @@ MUTANTS = {
                                     "if (1)"),
     "poly counts only the reported attempt": ("  best.iters = iters;\n", "  best.iters = best.iters;\n"),
     "poly stage order": ("{OR_ALG_NEWTON, OR_ALG_ARMIJO, OR_ALG_DOGLEG}", "{OR_ALG_NEWTON, OR_ALG_DOGLEG, OR_ALG_ARMIJO}"),
+    "tangent sign": ("      du[i] = -s;\n", "      du[i] = s;\n"),
+    "adjoint gradient sign": ("      grad[j] = -s;\n", "      grad[j] = s;\n"),
+    "adjoint solves with J, not J^T": ("for (j = 0; j < n; ++j) Jt[i * n + j] = J[j * n + i];",
+                                       "for (j = 0; j < n; ++j) Jt[i * n + j] = J[i * n + j];"),
+    "parameter seed on the wrong entry": ("for (i = 0; i < P; ++i) pd[i] = dl(p[i], i == j ? 1.0 : 0.0);",
+                                          "for (i = 0; i < P; ++i) pd[i] = dl(p[i], i == (j + 1) % P ? 1.0 : 0.0);"),
+    "tanh parameter derivative uses u": ("s = dadd(s, dmul(A[i * n + j], dconst(tanh(u[j]))));",
+                                         "s = dadd(s, dmul(A[i * n + j], dconst(u[j])));"),
     "iteration count off by one": ("r.retcode = OR_RC_SUCCESS; r.iters = k; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)",
                                    "r.retcode = OR_RC_SUCCESS; r.iters = k + 1; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)"),
 }
