@@ -226,6 +226,57 @@ const char* nls_last_error(const nls_context* c);
  * NLS_CTX_AUTOTUNE.  Errors: NLS_E_INVALID.                                 */
 int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precision, int32_t* lanes_per_system);
 
+/* ---- sensitivities at a solution (Sec. 2.3) ------------------------------
+ * At a root u* of F(u, theta) = 0 whose Jacobian J = dF/du is nonsingular,
+ * the implicit function theorem gives the derivative of u* in the parameters
+ * theta as D = -J^{-1} dF/dtheta (the theorem's minus sign).  Per system:
+ *   TANGENT : du = D v for a parameter direction v (one solve with J);
+ *   ADJOINT : lambda = J^{-T} w and grad = w^T D = -(dF/dtheta)^T lambda,
+ *             the gradient of w . u* in theta (one solve with J^T).
+ * J is formed afresh at u*; dF/dtheta are the families' parameter
+ * derivatives (the forward-mode tangents of their residuals). FP64 only.   */
+#define NLS_SENS_TANGENT 0
+#define NLS_SENS_ADJOINT 1
+
+/* A batch of M solved systems.  family/n, params/p_offset and u/u_offset
+ * follow nls_batch (u: the solutions, laid out like u0 there).
+ *   seed : TANGENT: v, laid out like params (same p_offset);
+ *          ADJOINT: w, laid out like u (same u_offset).                   */
+typedef struct {
+  int64_t count;
+  const uint8_t* family;
+  const uint8_t* n;
+  uint8_t family_all;
+  uint8_t n_all;
+  uint8_t mode;         /* NLS_SENS_*                                        */
+  uint8_t reserved;
+  uint32_t mem_kind;    /* NLS_MEM_* for params, u, seed and every result    */
+  const double* params;
+  const int64_t* p_offset;
+  const double* u;
+  const int64_t* u_offset;
+  const double* seed;
+} nls_sens_batch;
+
+/* Results (caller-owned; entries in offset gaps are left as they are):
+ *   out    : TANGENT: du, laid out like u; ADJOINT: the gradient, laid out
+ *            like params (may be NULL when no system has parameters)
+ *   lambda : ADJOINT only, may be NULL: J^{-T} w, laid out like u
+ *   status : [M] NLS_RC_SUCCESS, NLS_RC_SINGULAR (a zero or non-finite
+ *            pivot in the LU of J) or NLS_RC_NONFINITE (u, params or J not
+ *            finite); the system's outputs are NaN unless SUCCESS.           */
+typedef struct {
+  double* out;
+  double* lambda;
+  int32_t* status;
+} nls_sens_results;
+
+/* Validate, then enqueue the sensitivities of batch b writing r; tickets and
+ * payload rules as in nls_solve_batch (host payloads: synchronous).
+ * Errors: NLS_E_INVALID (bad mode, family/size, offsets or NULL arrays),
+ * NLS_E_NOMEM, NLS_E_DEVICE.                                                 */
+int nls_sensitivity_batch(nls_context* c, const nls_sens_batch* b, const nls_sens_results* r, uint64_t* ticket);
+
 /* Number of float64 parameters of a family at size n, or -1 if invalid.      */
 int nls_nparams(int family, int n);
 

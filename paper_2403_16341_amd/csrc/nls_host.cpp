@@ -931,4 +931,209 @@ int nls_query(nls_context* c, uint64_t ticket, int32_t wait_ms, nls_ticket_info*
   return status == NLS_OK ? NLS_OK : NLS_E_DEVICE;
 }
 
+// Sensitivities at a solution: validation, payload staging and one launch
+// per (family, size bucket).
+static std::string validate_sens(const nls_sens_batch* b, const nls_sens_results* r, int64_t* ptotal,
+                                 int64_t* utotal) {
+  *ptotal = *utotal = 0;
+  if (!b) return "batch is NULL";
+  if (b->count < 0) return "count must be >= 0";
+  if (b->count > (int64_t)INT32_MAX) return "count exceeds 2^31 - 1";
+  if (b->mode != NLS_SENS_TANGENT && b->mode != NLS_SENS_ADJOINT) return "unknown sensitivity mode";
+  if (b->mem_kind != NLS_MEM_HOST && b->mem_kind != NLS_MEM_DEVICE) return "unknown mem_kind";
+  const int64_t M = b->count;
+  if (M == 0) return "";
+  int64_t pacc = 0, uacc = 0;
+  for (int64_t s = 0; s < M; ++s) {
+    const int fam = b->family ? b->family[s] : b->family_all;
+    const int n = b->n ? b->n[s] : b->n_all;
+    char buf[160];
+    if (n < 1 || n > NLS_NMAX) {
+      std::snprintf(buf, sizeof buf, "system %lld: n = %d outside [1, 64]", (long long)s, n);
+      return buf;
+    }
+    if (fam < 0 || fam >= FAM_COUNT || !supported(fam, n)) {
+      std::snprintf(buf, sizeof buf, "system %lld: family %d is not defined at n = %d", (long long)s, fam, n);
+      return buf;
+    }
+    const int P = nparams_of(fam, n);
+    const int64_t po = b->p_offset ? b->p_offset[s] : pacc;
+    const int64_t uo = b->u_offset ? b->u_offset[s] : uacc;
+    if (b->p_offset && (po < 0 || b->p_offset[s + 1] - po < P)) {
+      std::snprintf(buf, sizeof buf, "system %lld: p_offset span shorter than %d parameters", (long long)s, P);
+      return buf;
+    }
+    if (b->u_offset && (uo < 0 || b->u_offset[s + 1] - uo < n)) {
+      std::snprintf(buf, sizeof buf, "system %lld: u_offset span shorter than n = %d", (long long)s, n);
+      return buf;
+    }
+    pacc = po + P;
+    uacc = uo + n;
+    *ptotal = std::max(*ptotal, pacc);
+    *utotal = std::max(*utotal, uacc);
+  }
+  if (b->p_offset) *ptotal = std::max(*ptotal, b->p_offset[M]);
+  if (b->u_offset) *utotal = std::max(*utotal, b->u_offset[M]);
+  const bool tangent = b->mode == NLS_SENS_TANGENT;
+  if (!b->u) return "u is NULL";
+  if (*ptotal > 0 && !b->params) return "params is NULL";
+  if ((tangent ? *ptotal : *utotal) > 0 && !b->seed) return "seed is NULL";
+  if (!r) return "results is NULL";
+  if (!r->status) return "status is NULL";
+  if ((tangent ? *utotal : *ptotal) > 0 && !r->out) return "out is NULL";
+  return "";
+}
+
+int nls_sensitivity_batch(nls_context* c, const nls_sens_batch* b, const nls_sens_results* r, uint64_t* ticket) {
+  if (!c) return fail(nullptr, NLS_E_INVALID, "context is NULL");
+  std::unique_lock<std::mutex> lk(c->mu, std::defer_lock);
+  if (c->flags & NLS_CTX_THREADSAFE) lk.lock();
+  if (!ticket) return fail(c, NLS_E_INVALID, "ticket is NULL");
+  int64_t ptotal = 0, utotal = 0;
+  const std::string m = validate_sens(b, r, &ptotal, &utotal);
+  if (!m.empty()) return fail(c, NLS_E_INVALID, m);
+  const int64_t M = b->count;
+  const bool dev = b->mem_kind == NLS_MEM_DEVICE;
+  const bool tangent = b->mode == NLS_SENS_TANGENT;
+  const bool uniform = !b->family && !b->n && !b->p_offset && !b->u_offset;
+  const int64_t seed_len = tangent ? ptotal : utotal, out_len = tangent ? utotal : ptotal;
+  const bool want_lambda = !tangent && r->lambda;
+
+  uint64_t need = 0;
+  if (!dev) need += (uint64_t)(ptotal + utotal + seed_len + out_len + (want_lambda ? utotal : 0)) * 8 + M * 4;
+  if (!uniform) need += (uint64_t)M * (4 + 1 + 16) + 16;
+  if (c->budget && c->held_bytes + need > c->budget) {
+    if (need > c->budget) return fail(c, NLS_E_NOMEM, "batch needs more device memory than the budget");
+    return fail(c, NLS_E_NOMEM, "budget exhausted by outstanding tickets; query them first");
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+
+  Ticket t;
+  t.systems = M;
+  uint64_t held = 0;
+  DevBuf db{&t.device_allocs, &held};
+  auto bail = [&](hipError_t err, const char* what) {
+    hipStreamSynchronize(c->stream);
+    release_ticket(t, c);
+    return hip_fail(c, err, what);
+  };
+  if ((e = hipEventCreate(&t.start)) != hipSuccess) return bail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&t.stop)) != hipSuccess) return bail(e, "hipEventCreate");
+  if ((e = hipEventRecord(t.start, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+
+  SensArgs a{};
+  a.params = b->params;
+  a.u = b->u;
+  a.seed = b->seed;
+  a.out = r->out;
+  a.lambda = want_lambda ? r->lambda : nullptr;
+  a.status = r->status;
+  if (M > 0 && !dev) {
+    // stage the inputs; the outputs start from the caller's arrays so that
+    // entries in offset gaps come back unchanged
+    struct Stage { const void* src; void** dst; int64_t bytes; bool out; };
+    void *pp = nullptr, *pu = nullptr, *ps = nullptr, *po = nullptr, *pl = nullptr, *pst = nullptr;
+    const Stage st[] = {{b->params, &pp, ptotal * 8, false}, {b->u, &pu, utotal * 8, false},
+                        {b->seed, &ps, seed_len * 8, false}, {r->out, &po, out_len * 8, true},
+                        {want_lambda ? r->lambda : nullptr, &pl, want_lambda ? utotal * 8 : 0, true}};
+    for (const Stage& x : st) {
+      if (!x.src || x.bytes == 0) continue;
+      if ((e = db.alloc(x.dst, x.bytes)) != hipSuccess) return bail(e, "hipMalloc");
+      if ((e = hipMemcpyAsync(*x.dst, x.src, x.bytes, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return bail(e, "hipMemcpyAsync");
+    }
+    if ((e = db.alloc(&pst, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    a.params = (const double*)pp;
+    a.u = (const double*)pu;
+    a.seed = (const double*)ps;
+    a.out = (double*)po;
+    a.lambda = (double*)pl;
+    a.status = (int32_t*)pst;
+  }
+
+  if (M > 0 && uniform) {
+    a.count = M;
+    a.n = b->n_all;
+    a.P = nparams_of(b->family_all, b->n_all);
+    const int rc = launch_sens(sens_bucket(b->n_all), b->family_all, b->mode, a, c->stream);
+    if (rc < 0) return bail((hipError_t)(-rc), "kernel launch");
+    if (rc > 0) return fail(c, NLS_E_INVALID, "no sensitivity kernel for this family/size");
+  } else if (M > 0) {
+    // counting sort on (family, size bucket); one launch per key
+    constexpr int kKeys = FAM_COUNT * 8;
+    std::vector<int64_t> poff(M + 1), uoff(M + 1);
+    std::vector<uint8_t> nn(M), key(M);
+    int64_t pacc = 0, uacc = 0;
+    for (int64_t s = 0; s < M; ++s) {
+      const int fam = b->family ? b->family[s] : b->family_all;
+      const int n = b->n ? b->n[s] : b->n_all;
+      poff[s] = b->p_offset ? b->p_offset[s] : pacc;
+      uoff[s] = b->u_offset ? b->u_offset[s] : uacc;
+      pacc = poff[s] + nparams_of(fam, n);
+      uacc = uoff[s] + n;
+      nn[s] = (uint8_t)n;
+      key[s] = (uint8_t)(fam * 8 + sens_bucket(n) / 8 - 1);
+    }
+    poff[M] = pacc;
+    uoff[M] = uacc;
+    std::vector<int64_t> cnt(kKeys + 1, 0);
+    for (int64_t s = 0; s < M; ++s) cnt[key[s] + 1]++;
+    for (int i = 0; i < kKeys; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> order(M);
+    {
+      std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
+      for (int64_t s = 0; s < M; ++s) order[at[key[s]]++] = (int32_t)s;
+    }
+    void *dsys = nullptr, *dpo = nullptr, *duo = nullptr, *dn = nullptr;
+    if ((e = db.alloc(&dsys, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&dpo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&duo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = db.alloc(&dn, M)) != hipSuccess) return bail(e, "hipMalloc");
+    if ((e = hipMemcpyAsync(dsys, order.data(), M * 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(dpo, poff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(duo, uoff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(dn, nn.data(), M, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    // the host vectors die with this call: the copies complete first
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+    for (int k = 0; k < kKeys; ++k) {
+      if (cnt[k + 1] == cnt[k]) continue;
+      SensArgs x = a;
+      x.sys = (const int32_t*)dsys + cnt[k];
+      x.count = cnt[k + 1] - cnt[k];
+      x.p_off = (const int64_t*)dpo;
+      x.u_off = (const int64_t*)duo;
+      x.nsys = (const uint8_t*)dn;
+      x.P = 0;
+      x.n = 0;
+      const int rc = launch_sens((k % 8 + 1) * 8, k / 8, b->mode, x, c->stream);
+      if (rc < 0) return bail((hipError_t)(-rc), "kernel launch");
+      if (rc > 0) return fail(c, NLS_E_INVALID, "no sensitivity kernel for this family/size");
+    }
+  }
+
+  if (M > 0 && !dev) {
+    if (out_len && r->out &&
+        (e = hipMemcpyAsync(r->out, a.out, out_len * 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if (want_lambda && (e = hipMemcpyAsync(r->lambda, a.lambda, utotal * 8, hipMemcpyDeviceToHost, c->stream)) !=
+                           hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+    if ((e = hipMemcpyAsync(r->status, a.status, M * 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(e, "hipMemcpyAsync");
+  }
+  if ((e = hipEventRecord(t.stop, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+  if (!dev && (e = hipEventSynchronize(t.stop)) != hipSuccess) return bail(e, "hipEventSynchronize");
+  const uint64_t id = c->next_ticket++;
+  t.bytes = held;
+  c->held_bytes += held;
+  c->tickets.emplace(id, std::move(t));
+  *ticket = id;
+  return NLS_OK;
+}
+
 }  // extern "C"

@@ -54,6 +54,29 @@ struct PolyMergeArgs {
 };
 int launch_poly_merge(const PolyMergeArgs& a, hipStream_t st);
 
+// Sensitivities at a solution (implicit function theorem).  Slot t handles
+// system sys[t] (or t when sys is null); the parameters of system s start at
+// params + p_off[s] (or s * P), its unknowns at u + u_off[s] (or s * n).
+enum : int { SENS_TANGENT = 0, SENS_ADJOINT = 1 };
+struct SensArgs {
+  const double* params;
+  const double* u;     // the solution u*
+  const double* seed;  // tangent: v (laid out like params); adjoint: w (like u)
+  double* out;         // tangent: du (like u); adjoint: the gradient (like params)
+  double* lambda;      // adjoint: J^{-T} w (like u); may be null
+  int32_t* status;     // [M]: RC_SUCCESS, RC_SINGULAR or RC_NONFINITE
+  const int64_t* p_off;
+  const int64_t* u_off;
+  const int32_t* sys;
+  const uint8_t* nsys;  // per-system n, or null with n uniform
+  int64_t count;
+  int64_t P;
+  int32_t n;
+};
+// size bucket of the sensitivity kernels: 8, 16, 24, ..., 64
+inline int sens_bucket(int n) { return n <= 8 ? 8 : (n + 7) / 8 * 8; }
+int launch_sens(int nb, int fam, int mode, const SensArgs& a, hipStream_t st);
+
 // dispatch over the buckets 16, 24, ..., 64
 inline int launch_group(int prec, int nb, int fam, int alg, const KArgs& a, hipStream_t st) {
 #define NLS_CASE(NB) \

@@ -34,7 +34,8 @@ CTX_AUTOTUNE = 2
 EXPORTS = ("nls_create", "nls_destroy", "nls_solve_batch", "nls_query", "nls_validate",
            "nls_last_error", "nls_get_mapping", "nls_nparams", "nls_default_options", "nls_abi_version",
            "nls_server_create", "nls_server_submit", "nls_server_poll", "nls_server_stats_get",
-           "nls_server_destroy")
+           "nls_server_destroy", "nls_sensitivity_batch")
+SENS_TANGENT, SENS_ADJOINT = 0, 1
 
 
 class ContextDesc(ctypes.Structure):
@@ -66,6 +67,18 @@ class Batch(ctypes.Structure):
 class Results(ctypes.Structure):
     _fields_ = [("u", ctypes.c_void_p), ("fnorm_inf", ctypes.c_void_p), ("iters", ctypes.c_void_p),
                 ("retcode", ctypes.c_void_p), ("nfev", ctypes.c_void_p), ("njev", ctypes.c_void_p)]
+
+
+class SensBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("family", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("family_all", ctypes.c_uint8), ("n_all", ctypes.c_uint8), ("mode", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8), ("mem_kind", ctypes.c_uint32),
+                ("params", ctypes.c_void_p), ("p_offset", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("u_offset", ctypes.c_void_p), ("seed", ctypes.c_void_p)]
+
+
+class SensResults(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class TicketInfo(ctypes.Structure):
@@ -145,6 +158,9 @@ def lib() -> ctypes.CDLL:
     L.nls_server_stats_get.restype = ctypes.c_int
     L.nls_server_destroy.argtypes = [P]
     L.nls_server_destroy.restype = ctypes.c_int
+    L.nls_sensitivity_batch.argtypes = [P, ctypes.POINTER(SensBatch), ctypes.POINTER(SensResults),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+    L.nls_sensitivity_batch.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -253,6 +269,30 @@ class Context:
             raise NLSError(rc, self.error())
         return t.value, (fa, na, aa, po, uo, params, u0, keep)
 
+    def submit_sensitivity(self, *, count, family, n, mode, params, u, seed, p_offset=None,
+                           u_offset=None, mem_kind=MEM_DEVICE, out=None, lam=None, status=None):
+        """Enqueue sensitivities of solved systems (tangent: du for direction
+        ``seed``; adjoint: the gradient of seed . u* and, if ``lam`` is given,
+        J^{-T} seed); returns (ticket, keepalive)."""
+        b = SensBatch()
+        b.count = int(count)
+        fa, na = _host_u8(family, count), _host_u8(n, count)
+        b.family, b.n = _ptr(fa), _ptr(na)
+        b.family_all = 0 if fa is not None else int(family)
+        b.n_all = 0 if na is not None else int(n)
+        b.mode = int(mode)
+        b.mem_kind = int(mem_kind)
+        po = None if p_offset is None else np.ascontiguousarray(p_offset, dtype=np.int64)
+        uo = None if u_offset is None else np.ascontiguousarray(u_offset, dtype=np.int64)
+        b.params, b.u, b.seed = _ptr(params), _ptr(u), _ptr(seed)
+        b.p_offset, b.u_offset = _ptr(po), _ptr(uo)
+        r = SensResults(_ptr(out), _ptr(lam), _ptr(status))
+        t = ctypes.c_uint64(0)
+        rc = lib().nls_sensitivity_batch(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.byref(t))
+        if rc != OK:
+            raise NLSError(rc, self.error())
+        return t.value, (fa, na, po, uo, params, u, seed, out, lam, status)
+
     def query(self, ticket: int, wait_ms: int = -1):
         info = TicketInfo()
         rc = lib().nls_query(self.handle, ctypes.c_uint64(ticket), int(wait_ms), ctypes.byref(info))
@@ -315,6 +355,49 @@ class DeviceBatch:
 def results_to_numpy(out: dict) -> dict:
     return {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in out.items()
             if not k.startswith("_")}
+
+
+def sensitivities(ctx: Context, b: "_inputs.Batch", u, seed, mode: int, mem_kind: int = MEM_DEVICE,
+                  want_lambda: bool = True) -> dict:
+    """Sensitivities of the systems of ``b`` at the solutions ``u`` (laid out
+    like ``b.u0``) through the device (MEM_DEVICE) or host (MEM_HOST) payload
+    path; returns numpy arrays out, lambda (adjoint), status and gpu_ms."""
+    M = b.M
+    uni = b.uniform()
+    packed = M > 0 and uni is not None and b.p_off[0] == 0 and b.u_off[0] == 0 and \
+        (np.diff(b.p_off) == nls_params(uni[0], uni[1])).all() and (np.diff(b.u_off) == uni[1]).all()
+    fam, n = (uni[0], uni[1]) if packed else (b.family, b.n)
+    po, uo = (None, None) if packed else (b.p_off, b.u_off)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    seed = np.ascontiguousarray(seed, dtype=np.float64)
+    params = b.params if b.params.size else np.zeros(1)
+    out_len = b.u0.size if mode == SENS_TANGENT else max(b.params.size, 1)
+    adj = mode == SENS_ADJOINT and want_lambda
+    if mem_kind == MEM_DEVICE:
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda(ctx.device)
+        dp, du_, ds = dev(params), dev(u), dev(seed if seed.size else np.zeros(1))
+        out = torch.full((out_len,), float("nan"), dtype=torch.float64, device="cuda")
+        lam = torch.full((max(b.u0.size, 1),), float("nan"), dtype=torch.float64, device="cuda") if adj else None
+        st = torch.full((max(M, 1),), -1, dtype=torch.int32, device="cuda")
+        t, keep = ctx.submit_sensitivity(count=M, family=fam, n=n, mode=mode, params=dp, u=du_, seed=ds,
+                                         p_offset=po, u_offset=uo, mem_kind=MEM_DEVICE, out=out, lam=lam,
+                                         status=st)
+        info = ctx.query(t, -1)
+        res = dict(out=out.cpu().numpy(), status=st.cpu().numpy()[:M], gpu_ms=info.gpu_ms)
+        if adj:
+            res["lambda"] = lam.cpu().numpy()[: b.u0.size]
+        return res
+    out = np.full(out_len, np.nan)
+    lam = np.full(max(b.u0.size, 1), np.nan) if adj else None
+    st = np.full(max(M, 1), -1, dtype=np.int32)
+    t, keep = ctx.submit_sensitivity(count=M, family=fam, n=n, mode=mode, params=params, u=u,
+                                     seed=seed if seed.size else np.zeros(1), p_offset=po, u_offset=uo,
+                                     mem_kind=MEM_HOST, out=out, lam=lam, status=st)
+    info = ctx.query(t, -1)
+    res = dict(out=out, status=st[:M], gpu_ms=info.gpu_ms)
+    if adj:
+        res["lambda"] = lam[: b.u0.size]
+    return res
 
 
 def solve_host(ctx: Context, b: "_inputs.Batch", precision: int | None = None, opts=None) -> dict:

@@ -142,3 +142,14 @@ def test_fallback_chain_is_an_algorithm(nls):
     b, keep = _batch(nls)
     b.alg = algs.ctypes.data_as(ctypes.c_void_p)
     assert nls.lib().nls_validate(ctypes.byref(b), None) == nls.OK
+
+
+def test_sensitivity_entry_rejects_null_context(nls):
+    """The sensitivity entry point checks its context before anything else
+    (no device needed)."""
+    L = nls.lib()
+    b = nls.SensBatch()
+    r = nls.SensResults()
+    t = ctypes.c_uint64(0)
+    assert L.nls_sensitivity_batch(None, ctypes.byref(b), ctypes.byref(r), ctypes.byref(t)) == nls.E_INVALID
+    assert nls.SENS_TANGENT == 0 and nls.SENS_ADJOINT == 1
