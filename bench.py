@@ -156,7 +156,45 @@ def extra_workloads(nls, ctx, args):
         out[name] = entry
         del db
         torch.cuda.empty_cache()
+    out["tanh_n16_adjoint_262144"] = sensitivity_workload(nls, ctx)
     return out
+
+
+def sensitivity_workload(nls, ctx):
+    """Adjoint sensitivities (gradient of w . u* in the parameters, Sec. 2.3)
+    of the 262,144 x N=16 tanh systems at their own FP64 solutions."""
+    from paper_2403_16341_amd import inputs
+    import torch
+    b = inputs.config(3)
+    db = nls.DeviceBatch(b)
+    sol = ctx.solve(db)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20240316)
+    w = torch.randn(b.u0.size, dtype=torch.float64, device="cuda", generator=gen)
+    grad = torch.empty(b.params.size, dtype=torch.float64, device="cuda")
+    lam = torch.empty(b.u0.size, dtype=torch.float64, device="cuda")
+    st = torch.empty(b.M, dtype=torch.int32, device="cuda")
+    kw = dict(count=b.M, family=inputs.TANH, n=16, mode=nls.SENS_ADJOINT, params=db.params, u=sol["u"],
+              seed=w, out=grad, lam=lam, status=st)
+    for _ in range(2):
+        ctx.query(ctx.submit_sensitivity(**kw)[0], -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [ctx.submit_sensitivity(**kw)[0] for _ in range(5)]
+    gms = [ctx.query(t, -1).gpu_ms for t in tickets]
+    torch.cuda.synchronize()
+    step = (time.perf_counter() - t0) / 5
+    n, P = 16, 16 * 16 + 16 + 1
+    # algorithmic bytes per system: params, u, w in; gradient, lambda, status out
+    nbytes = 8 * (P + n + n) + 8 * (P + n) + 4
+    kms = float(np.mean(gms))
+    ok = int((st == 0).sum().item())
+    print("[bench] tanh_n16_adjoint_262144: %.3f ms/step, %d nonsingular" % (step * 1e3, ok),
+          file=sys.stderr, flush=True)
+    return {"systems": b.M, "value": b.M / step, "unit": "systems/s", "ms_per_step": step * 1e3,
+            "kernel_ms": kms, "status_success": ok, "bytes_per_system": nbytes,
+            "hbm_gbs": nbytes * b.M / (kms * 1e-3) / 1e9,
+            "hbm_frac": nbytes * b.M / (kms * 1e-3) / 1e9 / 8000.0}
 
 
 def _pct(x, q):
