@@ -7,7 +7,7 @@ GPU path computes, written from the paper (arXiv 2403.16341):
 * Jacobians by forward-mode dual numbers, one JVP per column (Sec. 2.4),
 * LU with partial pivoting, LAPACK getrf pivot rule (Sec. 3.2 small dense LU),
 * Newton-Raphson (Sec. 2.1), Armijo backtracking (Sec. 2.2.1), Powell dogleg
-  trust region (Sec. 2.2.2),
+  trust region (Sec. 2.2.2), the Potra-Ptak two-step scheme (Sec. 2.1),
 * the first-order part of the default poly-algorithm (Sec. 3.2): the three
   methods above in turn, each from the starting point, until one succeeds,
 * sensitivities at a solution by the implicit function theorem (Sec. 2.3),
@@ -29,7 +29,7 @@ _SRC = os.path.join(_HERE, "nls_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CUBIC, TANH, ROSENBROCK, PAPER = 0, 1, 2, 3
-NEWTON, ARMIJO, DOGLEG, POLY = 0, 1, 2, 3
+NEWTON, ARMIJO, DOGLEG, POLY, POTRA_PTAK = 0, 1, 2, 3, 4
 RC_SUCCESS, RC_MAXITERS, RC_SINGULAR, RC_NONFINITE, RC_LINESEARCH_FAILED, RC_TR_COLLAPSED = range(6)
 
 # trace columns (mirror of the OR_TR_* enum in nls_oracle.h)

@@ -484,6 +484,44 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
     goto done;
   }
 
+  if (alg == OR_ALG_POTRA_PTAK) {
+    /* Sec. 2.1, multi-step scheme of Potra and Ptak: one Jacobian, two solves.
+     *   J_k d1 = -f(u_k),  y_k = u_k + d1,  J_k d2 = -f(y_k),  u_{k+1} = y_k + d2.
+     * The stopping test applies to the iterates u_k; a non-finite f(y_k) ends
+     * the iteration (NONFINITE, reporting y_k). */
+    for (k = 1; k <= maxiters; ++k) {
+      double mb = sumsq(n, F);
+      r.njev += 1;
+      if (newton_direction(family, n, p, u, F, J, lu, piv, delta)) {
+        r.retcode = OR_RC_SINGULAR; r.iters = k; goto done;
+      }
+      for (i = 0; i < n; ++i) ut[i] = u[i] + delta[i];
+      or_residual(family, n, p, ut, Ft);
+      r.nfev += 1;
+      if (!all_finite(n, Ft)) {
+        memcpy(u, ut, sizeof(double) * n);
+        memcpy(F, Ft, sizeof(double) * n);
+        r.retcode = OR_RC_NONFINITE; r.iters = k; goto done;
+      }
+      /* the same factors, right-hand side -f(y_k) */
+      for (i = 0; i < n; ++i) step[i] = -Ft[i];
+      or_lu_solve(n, lu, piv, step);
+      for (i = 0; i < n; ++i) u[i] = ut[i] + step[i];
+      or_residual(family, n, p, u, F);
+      r.nfev += 1;
+      row_clear(row);
+      row[OR_TR_K] = k; row[OR_TR_MERIT_BEFORE] = mb;
+      row[OR_TR_STEP] = sqrt(sumsq(n, delta)); row[OR_TR_NEWTON_NORM] = sqrt(sumsq(n, step));
+      row[OR_TR_FINF] = report_norm(n, F); row[OR_TR_MERIT] = sumsq(n, F);
+      row[OR_TR_ACCEPTED] = 1;
+      trace_row(trace, trace_cap, trace_len, row);
+      if (!all_finite(n, F)) { r.retcode = OR_RC_NONFINITE; r.iters = k; goto done; }
+      if (norm_inf(n, F) <= abstol) { r.retcode = OR_RC_SUCCESS; r.iters = k; goto done; }
+    }
+    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;
+    goto done;
+  }
+
   if (alg == OR_ALG_ARMIJO) {
     /* Sec. 2.2.1: backtracking from alpha = 1 by the factor rho until
      * phi(alpha) <= phi(0) + c alpha f^T J delta, with phi = 0.5 ||f||_2^2.

@@ -17,6 +17,7 @@
  *   NEWTON ................. Sec. 2.1 eq. (newton_descent), L-inf stopping test
  *   NEWTON_ARMIJO .......... Sec. 2.2.1 eq. (sufficient-decrease), backtracking
  *   DOGLEG ................. Sec. 2.2.2 eq. (tr_subproblem), ratio rho_k, Powell dogleg
+ *   POTRA_PTAK ............. Sec. 2.1 multi-step scheme: two solves with one Jacobian
  *   POLY ................... Sec. 3.2 default poly-algorithm, first-order part
  *                            (Newton, then Newton with line search, then trust region)
  *   sensitivities .......... Sec. 2.3, implicit function theorem (tangent and adjoint)
@@ -31,7 +32,7 @@ extern "C" {
 #endif
 
 enum { OR_FAM_CUBIC = 0, OR_FAM_TANH = 1, OR_FAM_ROSENBROCK = 2, OR_FAM_PAPER = 3 };
-enum { OR_ALG_NEWTON = 0, OR_ALG_ARMIJO = 1, OR_ALG_DOGLEG = 2, OR_ALG_POLY = 3 };
+enum { OR_ALG_NEWTON = 0, OR_ALG_ARMIJO = 1, OR_ALG_DOGLEG = 2, OR_ALG_POLY = 3, OR_ALG_POTRA_PTAK = 4 };
 enum {
   OR_RC_SUCCESS = 0, OR_RC_MAXITERS = 1, OR_RC_SINGULAR = 2, OR_RC_NONFINITE = 3,
   OR_RC_LINESEARCH_FAILED = 4, OR_RC_TR_COLLAPSED = 5

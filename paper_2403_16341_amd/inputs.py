@@ -313,6 +313,14 @@ def rosenbrock(M: int, n: int, seed: int, alg: int = NEWTON, u0: str = "uniform"
     return homogeneous(ROSENBROCK, n, alg, np.zeros((M, 0)), x, 1e-8, 1000, name="rosenbrock")
 
 
+def paper_gpu_workload(alg: int = NEWTON) -> Batch:
+    """The batch of the paper's GPU kernel example (Sec. 3.3): 1,024 generalized
+    Rosenbrock systems of 10 unknowns, each started from U(0,1)^10, Newton."""
+    b = rosenbrock(1024, 10, seed=SEED_BASE + 6, alg=alg)
+    b.name = "paper-gpu-rosenbrock"
+    return b
+
+
 def paper_example(M: int, seed: int, alg: int = NEWTON) -> Batch:
     """Workflow example of Sec. 3: p = (3, 7, 18) for system 0, random nearby p otherwise."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -96,6 +96,17 @@ def test_edge_families_and_cases(nls, ctx):
                 u_tol="bound" if b.name in ("rosenbrock", "paper-example") else "strict")
 
 
+def test_paper_gpu_workload(nls, ctx):
+    """The batch of the paper's GPU kernel example (Sec. 3.3): 1,024 x
+    generalized Rosenbrock N = 10 from U(0,1)^10, Newton; every system reaches
+    the unique root (1, ..., 1)."""
+    b = inputs.paper_gpu_workload()
+    g = run_gpu(nls, ctx, b)
+    compare(b, g, b.name, u_tol="bound")
+    assert (g["retcode"] == oracle.RC_SUCCESS).all()
+    assert np.abs(g["u"] - 1.0).max() <= 1e-8
+
+
 def test_nonfinite_maxiters_and_empty(nls, ctx):
     b = inputs.config(2, M=130)
     b.u0[8 * 3 + 2] = np.nan          # system 3 starts at NaN

@@ -59,6 +59,10 @@ MUTANTS = {
                                           "for (i = 0; i < P; ++i) pd[i] = dl(p[i], i == (j + 1) % P ? 1.0 : 0.0);"),
     "tanh parameter derivative uses u": ("s = dadd(s, dmul(A[i * n + j], dconst(tanh(u[j]))));",
                                          "s = dadd(s, dmul(A[i * n + j], dconst(u[j])));"),
+    "potra second solve uses f(u_k)": ("      for (i = 0; i < n; ++i) step[i] = -Ft[i];\n      or_lu_solve(n, lu, piv, step);",
+                                       "      for (i = 0; i < n; ++i) step[i] = -F[i];\n      or_lu_solve(n, lu, piv, step);"),
+    "potra second step subtracted": ("for (i = 0; i < n; ++i) u[i] = ut[i] + step[i];",
+                                     "for (i = 0; i < n; ++i) u[i] = ut[i] - step[i];"),
     "iteration count off by one": ("r.retcode = OR_RC_SUCCESS; r.iters = k; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)",
                                    "r.retcode = OR_RC_SUCCESS; r.iters = k + 1; goto done; }\n    }\n    r.retcode = OR_RC_MAXITERS; r.iters = maxiters;\n    goto done;\n  }\n\n  if (alg == OR_ALG_ARMIJO)"),
 }
