@@ -157,7 +157,23 @@ def extra_workloads(nls, ctx, args):
         del db
         torch.cuda.empty_cache()
     out["tanh_n16_adjoint_262144"] = sensitivity_workload(nls, ctx)
+    out["paper_gpu_rosenbrock_n10_1024"] = paper_gpu_workload(nls, ctx)
     return out
+
+
+def paper_gpu_workload(nls, ctx):
+    """The batch of the paper's GPU kernel example (Sec. 3.3): 1,024
+    generalized Rosenbrock systems, N = 10, from U(0,1)^10, Newton (FP64)."""
+    from paper_2403_16341_amd import inputs
+    b = inputs.paper_gpu_workload()
+    db = nls.DeviceBatch(b)
+    o, step, gms = run_form(nls, ctx, db, inputs.PREC_FP64, 20, 3, with_counters=True)
+    conv = int((o["retcode"].cpu().numpy() == 0).sum())
+    print("[bench] paper_gpu_rosenbrock_n10_1024: %.3f ms/step, %d converged" % (step * 1e3, conv),
+          file=sys.stderr, flush=True)
+    return {"systems": b.M, "value": conv / step, "unit": "solves/s", "ms_per_step": step * 1e3,
+            "kernel_ms": float(np.median(gms)), "converged": conv,
+            "mean_iters": float(o["iters"].cpu().numpy().mean())}
 
 
 def sensitivity_workload(nls, ctx):

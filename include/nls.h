@@ -78,6 +78,12 @@ extern "C" {
  * come from the returned attempt; iters, nfev and njev are totals over the
  * attempts run.  nls_solve_batch only (the request server refuses it).      */
 #define NLS_ALG_POLY 3
+/* Sec. 2.1, multi-step scheme of Potra and Ptak: per iteration one Jacobian
+ * J_k and two solves, J_k d1 = -F(u_k), y_k = u_k + d1, J_k d2 = -F(y_k),
+ * u_{k+1} = y_k + d2 (local order three).  The stopping test applies to u_k;
+ * a non-finite F(y_k) ends the system as NONFINITE with u = y_k.  Counters:
+ * njev = iters, nfev = 2 iters + 1.                                         */
+#define NLS_ALG_POTRA_PTAK 4
 
 /* ---- precision forms ----------------------------------------------------
  * FP64       : everything in binary64.

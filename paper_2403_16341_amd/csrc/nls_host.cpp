@@ -310,7 +310,7 @@ struct DevBuf {
   }
 };
 
-int tune_key(int n, int fam, int alg, int prec) { return ((n * FAM_COUNT + fam) * ALG_COUNT + alg) * 2 + prec; }
+int tune_key(int n, int fam, int alg, int prec) { return ((n * FAM_COUNT + fam) * ALG_KEYS + alg) * 2 + prec; }
 
 void save_tuning(nls_context* c, int key, int choice) {
   if (c->tune_cache_path.empty()) return;
@@ -837,7 +837,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       const int alg1 = poly ? ALG_NEWTON : alg;  // the chain starts with Newton
       const Mapping mp = choose_mapping(c, n, fam, alg1, b->precision, a, 0, c1 - c0, a.sys, a.p_off);
       if (mp.error) return bail(mp.error, "autotune");
-      const int kid = (mp.lane ? 0 : 1000) + mp.key_n * 16 + fam * ALG_KEYS + alg;
+      const int kid = (mp.lane ? 0 : 100000) + mp.key_n * 64 + fam * ALG_KEYS + alg;
       auto it = by_kernel.find(kid);
       if (it != by_kernel.end() && !mp.lane && launches[it->second].a.sys + launches[it->second].a.count == a.sys) {
         launches[it->second].a.count += a.count;  // adjacent in the sorted order

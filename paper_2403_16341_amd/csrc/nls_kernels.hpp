@@ -248,9 +248,14 @@ __device__ __forceinline__ float recip(float x) {
 // Lane LU with partial pivoting, RHS carried along (forward substitution is
 // applied while eliminating), then back substitution.  Returns false on a
 // zero or non-finite pivot.  x holds the RHS on entry, the solution on exit.
+// With KEEP the factors stay for lane_lu_resolve: the multipliers below the
+// diagonal, the pivot reciprocals on it, and the row exchanged at step k in
+// pr[k].  Exchanges move columns k.. only, so the multiplier of column k
+// stays in the position it was computed for, where the carried elimination
+// of a second right-hand side meets it again.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
+template <int N, typename T, bool KEEP = false>
+__device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N], int* pr = nullptr) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -277,6 +282,7 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
     // exchange rows k and p (columns k.. and the RHS) with selects; the whole
     // network is skipped when no lane of the wavefront needs an exchange (the
     // empty asm keeps the compiler from turning the branch into selects)
+    if constexpr (KEEP) pr[k] = p;
     if (__any(p != k)) {
       __asm__ volatile("" ::: "memory");
 #pragma unroll
@@ -300,6 +306,7 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
       const T l = a[i][k] * r;
+      if constexpr (KEEP) a[i][k] = l;
 #pragma unroll
       for (int j = k + 1; j < N; ++j) a[i][j] = __builtin_fma(-l, a[k][j], a[i][j]);
       x[i] = __builtin_fma(-l, x[k], x[i]);
@@ -313,6 +320,35 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N]) {
     x[i] = s * a[i][i];
   }
   return ok;
+}
+
+// Second right-hand side on the factors lane_lu_solve<KEEP> left: the same
+// exchanges and eliminations in the same interleaved order as the carried
+// right-hand side of the factorisation, then back substitution.
+template <int N, typename T>
+__device__ __forceinline__ void lane_lu_resolve(const T (&a)[N][N], const int (&pr)[N], T (&x)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (__any(pr[k] != k)) {
+      __asm__ volatile("" ::: "memory");
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) {
+        const bool sel = (pr[k] == i);
+        T t = x[k];
+        x[k] = sel ? x[i] : t;
+        x[i] = sel ? t : x[i];
+      }
+    }
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) x[i] = __builtin_fma(-a[i][k], x[k], x[i]);
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    T s = x[i];
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) s = __builtin_fma(-a[i][j], x[j], s);
+    x[i] = s * a[i][i];
+  }
 }
 
 template <int N> __device__ __forceinline__ bool all_finite(const double (&F)[N]) {
@@ -580,7 +616,37 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         TI J[N][N];
         fam.template jacobian<TI>(u, aux, J);
         ++nj;
-        if (ALG != ALG_DOGLEG) {
+        if constexpr (ALG == ALG_POTRA) {
+          // J_k d1 = -F(u_k), y = u_k + d1; J_k d2 = -F(y) on the same factors;
+          // the trial point below is y + d2
+          TI x[N];
+          int pr[N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) x[i] = (TI)(-F[i]);
+          if (!lane_lu_solve<N, TI, true>(J, x, pr)) {
+            finish(RC_SINGULAR, k);
+          } else {
+            double Fy[N], auxy[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) u[i] = u[i] + (double)x[i];
+            fam.residual(u, Fy, auxy);
+            ++nf;
+#pragma unroll
+            for (int i = 0; i < N; ++i) { F[i] = Fy[i]; aux[i] = auxy[i]; }
+            if (!all_finite(F)) {
+              fcur = __builtin_inf();
+              phi = sumsq<N, double>(F);
+              finish(RC_NONFINITE, k);
+            } else {
+#pragma unroll
+              for (int i = 0; i < N; ++i) x[i] = (TI)(-F[i]);
+              lane_lu_resolve<N, TI>(J, pr, x);
+#pragma unroll
+              for (int i = 0; i < N; ++i) d[i] = (double)x[i];
+              st = ST_TRIAL;
+            }
+          }
+        } else if constexpr (ALG != ALG_DOGLEG) {
           // J_k delta = -F(u_k)
           TI x[N];
 #pragma unroll
@@ -646,7 +712,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       double ut[N], Ft[N], auxt[N];
       double step[N];
       double pred = 0.0;
-      if (ALG == ALG_NEWTON) {
+      if (ALG == ALG_NEWTON || ALG == ALG_POTRA) {
 #pragma unroll
         for (int i = 0; i < N; ++i) ut[i] = u[i] + d[i];
       } else if (ALG == ALG_ARMIJO) {
@@ -687,7 +753,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       }
       fam.residual(ut, Ft, auxt);
       ++nf;
-      if (ALG == ALG_NEWTON) {
+      if (ALG == ALG_NEWTON || ALG == ALG_POTRA) {
 #pragma unroll
         for (int i = 0; i < N; ++i) { u[i] = ut[i]; F[i] = Ft[i]; aux[i] = auxt[i]; }
         const bool fin1 = all_finite(F);
@@ -1031,13 +1097,16 @@ template <int NB> struct RowFam<NB, FAM_ROSENBROCK> {
 // unrolled fully (see the unroll threshold in the build), so every row index
 // is a constant and the row stays in registers.  On return the solution component r is in
 // sh.sol[gi][r].  Returns false (group-uniform) on a zero or non-finite pivot.
+// With the factors kept (J holds this row's multipliers left of its final
+// position and its row of U from there on; pos is that final position, myrd
+// the reciprocal of its pivot), group_lu_resolve solves for another RHS.
 template <int NB, int L, typename TI>
 __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
-                                               TI (&J)[NB], TI rhs) {
+                                               TI (&J)[NB], TI rhs, int& pos, TI& myrd) {
   const bool own = r < n;
-  int pos = own ? r : NB + 1 + r;  // logical row position; non-rows never pivot
+  pos = own ? r : NB + 1 + r;  // logical row position; non-rows never pivot
   bool ok = true;
-  TI myrd = TI(0);  // reciprocal of this row's pivot, once it has been the pivot row
+  myrd = TI(0);  // reciprocal of this row's pivot, once it has been the pivot row
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     if (k < n) {
@@ -1091,6 +1160,40 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
     }
   }
   return ok;
+}
+template <int NB, int L, typename TI>
+__device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
+                                               TI (&J)[NB], TI rhs) {
+  int pos;
+  TI myrd;
+  return group_lu_solve<NB, L, TI>(sh, gi, r, n, J, rhs, pos, myrd);
+}
+
+// Another right-hand side on the factors group_lu_solve kept: step k's pivot
+// row (final position k) publishes its updated RHS, the rows after it apply
+// their multipliers; then the same back substitution.  Solution in sh.sol.
+template <int NB, int L, typename TI>
+__device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
+                                                 const TI (&J)[NB], int pos, TI myrd, TI rhs) {
+  const bool own = r < n;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < n) {
+      if (pos == k) sh.piv[gi][NB] = rhs;
+      wave_sync();
+      if (own && pos > k) rhs = __builtin_fma(-J[k], sh.piv[gi][NB], rhs);
+      wave_sync();
+    }
+  }
+#pragma unroll
+  for (int k = NB - 1; k >= 0; --k) {
+    if (k < n) {
+      if (pos == k) sh.sol[gi][k] = rhs * myrd;
+      wave_sync();
+      if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
+      wave_sync();
+    }
+  }
 }
 
 // Persistent group-mapping kernel.  Each group of L lanes solves one system at
@@ -1218,7 +1321,29 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
       TI J[NB];
       fam.template jacobian_row<L, TI>(sh, sa, gi, r, own, u, aux, J);
       ++nj;
-      if constexpr (ALG != ALG_DOGLEG) {
+      if constexpr (ALG == ALG_POTRA) {
+        // J_k d1 = -F(u_k), y = u_k + d1; J_k d2 = -F(y) on the same factors;
+        // the trial point below is y + d2
+        int pos;
+        TI myrd;
+        if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, (TI)(-F), pos, myrd)) {
+          finish(RC_SINGULAR, k);
+        } else {
+          const double d1 = own ? (double)sh.sol[gi][r] : 0.0;
+          wave_sync();
+          u = u + d1;
+          F = fam.template residual<L, TI>(sh, sa, gi, r, own, u, aux);
+          ++nf;
+          if (!set_norms()) {
+            finish(RC_NONFINITE, k);
+          } else {
+            group_lu_resolve<NB, L, TI>(sh, gi, r, n, J, pos, myrd, (TI)(-F));
+            d = own ? (double)sh.sol[gi][r] : 0.0;
+            wave_sync();
+            gst = ST_TRIAL;
+          }
+        }
+      } else if constexpr (ALG != ALG_DOGLEG) {
         if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, (TI)(-F))) {
           finish(RC_SINGULAR, k);
         } else {
@@ -1262,7 +1387,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
     // ---------------- trial point, residual, decision ----------------
     if (gst == ST_TRIAL) {
       double ut, step = 0.0, pred = 0.0;
-      if (ALG == ALG_NEWTON) {
+      if (ALG == ALG_NEWTON || ALG == ALG_POTRA) {
         ut = u + d;
       } else if (ALG == ALG_ARMIJO) {
         ut = __builtin_fma(alpha, d, u);
@@ -1297,7 +1422,7 @@ __global__ __launch_bounds__(64) void k_group(const KArgs a) {
       ++nf;
       const bool fin_t = !grp_any<L>(!finite64(Ft));
       const double phit = grp_sum<L>(Ft * Ft);
-      if (ALG == ALG_NEWTON) {
+      if (ALG == ALG_NEWTON || ALG == ALG_POTRA) {
         u = ut;
         F = Ft;
         aux = auxt;

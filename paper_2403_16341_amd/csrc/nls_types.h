@@ -8,8 +8,9 @@ namespace nls {
 enum : int { FAM_CUBIC = 0, FAM_TANH = 1, FAM_ROSENBROCK = 2, FAM_PAPER = 3, FAM_COUNT = 4 };
 enum : int { ALG_NEWTON = 0, ALG_ARMIJO = 1, ALG_DOGLEG = 2, ALG_COUNT = 3 };
 // the fallback chain NEWTON -> ARMIJO -> DOGLEG, run by the host runtime as
-// three stages of the kernels above (no kernel of its own)
-enum : int { ALG_POLY = 3, ALG_KEYS = 4 };
+// three stages of the kernels above (no kernel of its own); the Potra-Ptak
+// two-step scheme (one Jacobian, two solves per iteration)
+enum : int { ALG_POLY = 3, ALG_POTRA = 4, ALG_KEYS = 5 };
 enum : int { PREC_FP64 = 0, PREC_FP32_INNER = 1 };
 enum : int {
   RC_SUCCESS = 0,

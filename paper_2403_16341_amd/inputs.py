@@ -23,7 +23,7 @@ import math
 import numpy as np
 
 CUBIC, TANH, ROSENBROCK, PAPER = 0, 1, 2, 3
-NEWTON, ARMIJO, DOGLEG, POLY = 0, 1, 2, 3
+NEWTON, ARMIJO, DOGLEG, POLY, POTRA_PTAK = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_INNER = 0, 1
 
 SEED_BASE = 20240316

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnls.so")
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_NOTFOUND = -1, -2, -3, -4
 FAMILY_CUBIC, FAMILY_TANH, FAMILY_ROSENBROCK, FAMILY_PAPER_EXAMPLE = 0, 1, 2, 3
-ALG_NEWTON, ALG_NEWTON_ARMIJO, ALG_DOGLEG, ALG_POLY = 0, 1, 2, 3
+ALG_NEWTON, ALG_NEWTON_ARMIJO, ALG_DOGLEG, ALG_POLY, ALG_POTRA_PTAK = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_INNER = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 RC_SUCCESS, RC_MAXITERS, RC_SINGULAR, RC_NONFINITE, RC_LINESEARCH_FAILED, RC_TR_COLLAPSED, RC_INVALID = range(7)

@@ -62,7 +62,7 @@ def _batch(nls, **kw):
 
 @pytest.mark.parametrize("bad,msg", [
     (dict(n=0), "n = 0"), (dict(n=65), "n = 65"), (dict(family=9), "family 9"),
-    (dict(alg=4), "algorithm 4"), (dict(family=3, n=3), "family 3"), (dict(family=2, n=1), "family 2"),
+    (dict(alg=5), "algorithm 5"), (dict(family=3, n=3), "family 3"), (dict(family=2, n=1), "family 2"),
     (dict(precision=2), "precision"), (dict(mem_kind=5), "mem_kind"), (dict(abstol=-1.0), "abstol"),
     (dict(abstol=float("nan")), "abstol"), (dict(maxiters=-1), "maxiters"), (dict(count=-1), "count"),
     (dict(u0=False), "u0"), (dict(params=False), "params"),
@@ -129,14 +129,17 @@ def test_fp32_inner_accepted_everywhere(nls):
 
 
 def test_fallback_chain_is_an_algorithm(nls):
-    """POLY (the Newton -> line search -> trust region chain) validates like
-    the single algorithms for every family and size; the next value does not."""
+    """POLY (the Newton -> line search -> trust region chain) and the
+    Potra-Ptak scheme validate like the other algorithms for every family and
+    size; the next value does not."""
     assert nls.ALG_POLY == 3
     for fam, n in ((0, 4), (0, 24), (1, 8), (1, 64), (2, 10), (3, 2)):
         for prec in (0, 1):
             b, keep = _batch(nls, family=fam, n=n, alg=nls.ALG_POLY, precision=prec)
             assert nls.lib().nls_validate(ctypes.byref(b), None) == nls.OK, (fam, n, prec)
-    b, keep = _batch(nls, alg=4)
+    b, keep = _batch(nls, alg=nls.ALG_POTRA_PTAK)
+    assert nls.lib().nls_validate(ctypes.byref(b), None) == nls.OK
+    b, keep = _batch(nls, alg=5)
     assert nls.lib().nls_validate(ctypes.byref(b), None) == nls.E_INVALID
     algs = np.array([0, 3, 3, 1], dtype=np.uint8)
     b, keep = _batch(nls)
