@@ -158,7 +158,29 @@ def extra_workloads(nls, ctx, args):
         torch.cuda.empty_cache()
     out["tanh_n16_adjoint_262144"] = sensitivity_workload(nls, ctx)
     out["paper_gpu_rosenbrock_n10_1024"] = paper_gpu_workload(nls, ctx)
+    out["cubic_n8_potra_ptak_1M"] = potra_ptak_workload(nls, ctx)
     return out
+
+
+def potra_ptak_workload(nls, ctx):
+    """The headline batch (2^20 x N=8 cubic, u0 ~ U(-3,3)) under the
+    Potra-Ptak two-step scheme instead of Newton + Armijo (FP64)."""
+    from paper_2403_16341_amd import inputs
+    import torch
+    b = inputs.config(2)
+    b.alg[:] = inputs.POTRA_PTAK
+    db = nls.DeviceBatch(b)
+    o, step, gms = run_form(nls, ctx, db, inputs.PREC_FP64, 10, 2, with_counters=True)
+    conv = int((o["retcode"].cpu().numpy() == 0).sum())
+    print("[bench] cubic_n8_potra_ptak_1M: %.3f ms/step, %d converged" % (step * 1e3, conv),
+          file=sys.stderr, flush=True)
+    res = {"systems": b.M, "value": conv / step, "unit": "solves/s", "ms_per_step": step * 1e3,
+           "kernel_ms": float(np.median(gms)), "converged": conv,
+           "mean_iters": float(o["iters"].cpu().numpy().mean()),
+           "mean_nfev": float(o["nfev"].cpu().numpy().mean())}
+    del db
+    torch.cuda.empty_cache()
+    return res
 
 
 def paper_gpu_workload(nls, ctx):
