@@ -440,8 +440,10 @@ def main():
     ap.add_argument("--leg", choices=("headline", "extras", "serving"), default=None,
                     help="run one leg in this process and print its JSON")
     ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")
-    ap.add_argument("--workload", choices=("headline", "tanh16", "cubic64", "cubic40"), default="headline",
-                    help="profiling: the batch --forms times (the headline, 2^18 x N=16 tanh dogleg, or "
+    ap.add_argument("--workload", choices=("headline", "tanh16", "tanh16poly", "adjoint16", "cubic64", "cubic40"),
+                    default="headline",
+                    help="profiling: the batch --forms times (the headline, 2^18 x N=16 tanh dogleg, the same under "
+                         "the fallback chain, adjoint sensitivities of it, or "
                          "16,384 x N=64 / N=40 cubic Armijo)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
@@ -485,10 +487,17 @@ def main():
 
     if args.forms:
         # profiling run: time one form in this process and stop
+        if args.workload == "adjoint16":
+            ctx = nls.Context(0)
+            print("[bench] %s" % json.dumps(sensitivity_workload(nls, ctx)), file=sys.stderr)
+            ctx.close()
+            return
         if args.workload == "headline":
             b = inputs.config(2, M=args.systems)
-        elif args.workload == "tanh16":
+        elif args.workload in ("tanh16", "tanh16poly"):
             b = inputs.config(3)
+            if args.workload == "tanh16poly":
+                b.alg[:] = inputs.POLY
         else:
             nn = 64 if args.workload == "cubic64" else 40
             rng = np.random.Generator(np.random.PCG64(7000 + nn))
