@@ -5,11 +5,11 @@
 // the gradient of w^T u* in theta, -(dF/dtheta)^T lambda, from one solve.
 //
 // One system per group of L lanes (L = 16, 32 or 64; several groups per
-// wavefront).  Lane r owns row r of the NB x NB matrix -- J for the tangent
-// form, J^T for the adjoint form -- padded with an identity block past n and
-// staged in LDS; Gaussian elimination with partial pivoting (first maximum in
-// row order, as LAPACK's getrf) runs on it with the right-hand side in
-// registers, then back substitution.  The parameter derivatives are the
+// wavefront).  Lane r holds row r of J (tangent form) or of J^T (adjoint
+// form) in registers and factorises it with the group LU of the solver
+// kernels (partial pivoting, first maximum in row order as LAPACK's getrf,
+// pivot search by butterfly over the group, pivot row broadcast through LDS),
+// the right-hand side carried along.  The parameter derivatives are the
 // families' forward-mode derivatives written out per row.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,15 +27,13 @@ template <int NB> struct SensWidth {
 template <int NB, int L, int FAM, int MODE>
 __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
   constexpr int G = 64 / L;
-  constexpr int LD = NB + 1;  // padded row stride (doubles)
-  __shared__ double m[G][NB][LD];
+  __shared__ __attribute__((aligned(16))) GroupShared<NB, L, double> sh;
   __shared__ double xs[G][NB];  // u
   __shared__ double ts[G][NB];  // tanh(u) (tanh family)
   const int lane = threadIdx.x;
   const int gi = lane / L;
   const int r = lane % L;
-  const bool row = r < NB;  // the lane owns a row of the padded matrix
-  const int src0 = gi * L;  // lane 0 of the group
+  const bool row = r < NB;
 
   for (int64_t base = (int64_t)blockIdx.x * G; base < a.count; base += (int64_t)gridDim.x * G) {
     const int64_t t = base + gi;
@@ -61,50 +59,49 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
     wave_sync();
     bool bad = own && !finite64(u);
 
-    // ---- row r of J (identity past n) and the right-hand side ----
-    double rhs = 0.0;
-    if (row) {
-      for (int j = 0; j < NB; ++j) {
-        double v = (j == r) ? 1.0 : 0.0;
-        if (own) {
-          v = 0.0;
-          if (j < n) {
-            if constexpr (FAM == FAM_CUBIC) {
-              const double aij = p[r * n + j];
-              bad |= !finite64(aij);
-              v = j == r ? aij + cubic_term_deriv(u) : aij;
-            } else if constexpr (FAM == FAM_TANH) {
-              const double aij = p[r * n + j];
-              bad |= !finite64(aij);
-              const double dphi = dtanh_known(dseed(xs[gi][j]), ts[gi][j]).d;
-              const double w = aij * dphi;
-              v = j == r ? w + p[n * n + n] : w;
-            } else if constexpr (FAM == FAM_ROSENBROCK) {
-              if (r == 0) {
-                v = j == 0 ? -1.0 : 0.0;
-              } else if (j == r - 1) {
-                const Dual<double> um = dseed(xs[gi][r - 1]);
-                v = (10.0 * (dconst(u) - um * um)).d;
-              } else if (j == r) {
-                v = (10.0 * (dseed(u) - dconst(xs[gi][r - 1]) * dconst(xs[gi][r - 1]))).d;
-              }
-            } else {  // the workflow example, n = 2
-              const Dual<double> x0 = {xs[gi][0], j == 0 ? 1.0 : 0.0};
-              const Dual<double> x1 = {xs[gi][1], j == 1 ? 1.0 : 0.0};
-              if (r == 0) {
-                const Dual<double> cube = x1 * x1 * x1;
-                v = ((x0 + dconst(p[0])) * (cube - dconst(p[1])) + dconst(p[2])).d;
-              } else {
-                v = dsin(x1 * dexp(x0) - dconst(1.0)).d;
-              }
-            }
-            bad |= !finite64(v);
+    // ---- this lane's row of J (tangent) or of J^T (adjoint), in registers ----
+    // entry (i, j) of J is dF_i/du_j, the forward-mode tangent of F_i for the
+    // seed u_j + eps; the adjoint form takes column r of J as its row r
+    double mrow[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double v = 0.0;
+      if (own && c < n) {
+        const int i = MODE == SENS_TANGENT ? r : c;  // row of J
+        const int j = MODE == SENS_TANGENT ? c : r;  // column of J
+        if constexpr (FAM == FAM_CUBIC) {
+          const double aij = p[i * n + j];
+          bad |= !finite64(aij);
+          v = i == j ? aij + cubic_term_deriv(xs[gi][i]) : aij;
+        } else if constexpr (FAM == FAM_TANH) {
+          const double aij = p[i * n + j];
+          bad |= !finite64(aij);
+          const double w = aij * dtanh_known(dseed(xs[gi][j]), ts[gi][j]).d;
+          v = i == j ? w + p[n * n + n] : w;
+        } else if constexpr (FAM == FAM_ROSENBROCK) {
+          if (i == 0) {
+            v = j == 0 ? -1.0 : 0.0;
+          } else if (j == i - 1) {
+            const Dual<double> um = dseed(xs[gi][i - 1]);
+            v = (10.0 * (dconst(xs[gi][i]) - um * um)).d;
+          } else if (j == i) {
+            v = (10.0 * (dseed(xs[gi][i]) - dconst(xs[gi][i - 1]) * dconst(xs[gi][i - 1]))).d;
+          }
+        } else {  // the workflow example, n = 2
+          const Dual<double> x0 = {xs[gi][0], j == 0 ? 1.0 : 0.0};
+          const Dual<double> x1 = {xs[gi][1], j == 1 ? 1.0 : 0.0};
+          if (i == 0) {
+            const Dual<double> cube = x1 * x1 * x1;
+            v = ((x0 + dconst(p[0])) * (cube - dconst(p[1])) + dconst(p[2])).d;
+          } else {
+            v = dsin(x1 * dexp(x0) - dconst(1.0)).d;
           }
         }
-        if constexpr (MODE == SENS_TANGENT) m[gi][r][j] = v;
-        else m[gi][j][r] = v;
+        bad |= !finite64(v);
       }
+      mrow[c] = v;
     }
+    double rhs = 0.0;
     if (own) {
       if constexpr (MODE == SENS_ADJOINT) {
         rhs = a.seed[uo + r];
@@ -131,57 +128,13 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
       if constexpr (FAM == FAM_PAPER) bad |= r == 0 && !(finite64(p[0]) && finite64(p[1]) && finite64(p[2]));
     }
     bad = grp_any<L>(bad);
-    wave_sync();
 
-    // ---- elimination with partial pivoting ----
-    bool sing = false;
-    for (int k = 0; k < NB; ++k) {
-      double cand = -1.0;
-      if (row && r >= k) {
-        const double c = __builtin_fabs(m[gi][r][k]);
-        cand = c == c ? c : -1.0;  // a NaN never wins the search
-      }
-      int idx = r;
-      grp_levels<L>([&](auto mc) {
-        constexpr int M = decltype(mc)::value;
-        const double oc = grp_partner<M, L>(cand);
-        const int oi = grp_partner<M, L>(idx);
-        if (oc > cand || (oc == cand && oi < idx)) {
-          cand = oc;
-          idx = oi;
-        }
-      });
-      const int piv = idx;
-      const double pk = m[gi][piv][k];
-      sing = sing || !(pk != 0.0 && finite64(pk));
-      const double r_k = __shfl(rhs, src0 + k, 64);
-      const double r_p = __shfl(rhs, src0 + piv, 64);
-      if (piv != k) {
-        if (row) {
-          const double x = m[gi][k][r];
-          m[gi][k][r] = m[gi][piv][r];
-          m[gi][piv][r] = x;
-        }
-        if (r == k) rhs = r_p;
-        else if (r == piv) rhs = r_k;
-      }
-      wave_sync();
-      const double rk = __shfl(rhs, src0 + k, 64);
-      if (row && r > k) {
-        const double l = m[gi][r][k] / pk;
-        for (int j = k + 1; j < NB; ++j) m[gi][r][j] = m[gi][r][j] - l * m[gi][k][j];
-        rhs = rhs - l * rk;
-      }
-      wave_sync();
-    }
-    // ---- back substitution: lane r ends with component r ----
-    for (int i = NB - 1; i >= 0; --i) {
-      if (r == i) rhs = rhs / m[gi][i][i];
-      const double xi = __shfl(rhs, src0 + i, 64);
-      if (row && r < i) rhs = rhs - m[gi][r][i] * xi;
-    }
-    const int32_t st = bad ? RC_NONFINITE : (sing ? RC_SINGULAR : RC_SUCCESS);
-    const double x = st == RC_SUCCESS ? rhs : __builtin_nan("");
+    // ---- LU with partial pivoting (first maximum in row order) and the
+    // triangular solves, the rows staying in registers ----
+    const bool ok = group_lu_solve<NB, L, double>(sh, gi, r, n, mrow, rhs);
+    const int32_t st = bad ? RC_NONFINITE : (ok ? RC_SUCCESS : RC_SINGULAR);
+    const double nan = __builtin_nan("");
+    const double x = (own && st == RC_SUCCESS) ? sh.sol[gi][r] : nan;
 
     // ---- outputs ----
     if constexpr (MODE == SENS_TANGENT) {
@@ -192,11 +145,13 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
       if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) {
         // dF_k/dA_kj = u_j (cubic) or tanh(u_j) (tanh): lane j writes column j
         const double phi = FAM == FAM_CUBIC ? u : tu;
-        for (int k = 0; k < NB; ++k) {
-          const double lk = __shfl(x, src0 + k, 64);
-          if (own && k < n) g[k * n + r] = -(lk * phi);
+        if (own) {
+          for (int k = 0; k < n; ++k) {
+            const double lk = st == RC_SUCCESS ? sh.sol[gi][k] : nan;
+            g[k * n + r] = -(lk * phi);
+          }
+          g[n * n + r] = x;  // dF_r/db_r = -1
         }
-        if (own) g[n * n + r] = x;  // dF_r/db_r = -1
         if constexpr (FAM == FAM_TANH) {
           const double sb = grp_sum<L>(own ? x * u : 0.0);  // dF_i/dbeta = u_i
           if (own && r == 0) g[n * n + n] = -sb;
