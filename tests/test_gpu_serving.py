@@ -214,3 +214,28 @@ def test_server_fp32_inner_alone_vs_mix(nls):
         succ = out["retcode"] == 0
         assert (out["retcode"] != nls.RC_INVALID).all()
         assert (out["fnorm_inf"][succ] <= rq.batch.abstol).all()
+
+
+def test_server_potra_ptak_requests_match_the_batch_path(nls):
+    """Potra-Ptak requests (lane and group kernels) through the server give
+    bitwise the results of the direct batch path, alone and merged."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    batches = []
+    for n, M in ((4, 150), (8, 90), (12, 60), (24, 20)):
+        p, u0 = inputs.cubic_params(rng, M, n), rng.uniform(-3, 3, (M, n))
+        batches.append(inputs.homogeneous(inputs.CUBIC, n, inputs.POTRA_PTAK, p, u0, 1e-10, 50))
+    ctx = nls.Context(0)
+    ref = [nls.solve_host(ctx, b) for b in batches]
+    ctx.close()
+    srv = nls.Server(0, mem_budget_bytes=64 << 20, streams=2)
+    ids = {}
+    for rep in range(2):
+        for j, b in enumerate(batches):
+            ids[srv.submit(b)] = j
+    done = srv.drain()
+    srv.close()
+    assert len(done) == 2 * len(batches)
+    for info, out in done:
+        assert info["status"] == 0
+        assert _same(out, ref[ids[info["id"]]])
+    assert all((r["retcode"] == 0).mean() > 0.9 for r in ref)
