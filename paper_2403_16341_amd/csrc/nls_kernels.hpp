@@ -1092,8 +1092,55 @@ template <int NB> struct RowFam<NB, FAM_ROSENBROCK> {
   }
 };
 
+// Value of x on lane src for every lane of the wavefront (src wave-uniform):
+// lane reads into scalar registers, no LDS round trip.
+__device__ __forceinline__ double wave_bcast(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float wave_bcast(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+// the one lane of the wavefront where pred holds (wave-uniform result)
+__device__ __forceinline__ int wave_lane_of(bool pred) { return __builtin_ctzll(__ballot(pred)); }
+
+// Back substitution over the kept factors, column by column from the last;
+// on return component k of the solution is in sh.sol[gi][k].
+template <int NB, int L, typename TI>
+__device__ __forceinline__ void group_back_substitute(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
+                                                      const TI (&J)[NB], int pos, TI myrd, TI rhs) {
+  const bool own = r < n;
+  if constexpr (L == 64) {
+    TI mine = TI(0);
+#pragma unroll
+    for (int k = NB - 1; k >= 0; --k) {
+      if (k < n) {
+        const TI xk = wave_bcast(rhs * myrd, wave_lane_of(pos == k));
+        if (r == k) mine = xk;
+        if (own && pos < k) rhs = __builtin_fma(-J[k], xk, rhs);
+      }
+    }
+    if (own) sh.sol[gi][r] = mine;
+    wave_sync();
+  } else {
+#pragma unroll
+    for (int k = NB - 1; k >= 0; --k) {
+      if (k < n) {
+        if (pos == k) sh.sol[gi][k] = rhs * myrd;
+        wave_sync();
+        if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
+        wave_sync();
+      }
+    }
+  }
+}
+
 // LU with partial pivoting of the group's rows (logical positions instead of
-// row exchanges), RHS carried along, then back substitution.  Both loops are
+// row exchanges), RHS carried along, then back substitution.  When the group
+// is the whole wavefront (L = 64) the pivot row and the solution components
+// travel by lane reads instead of through LDS.  Both loops are
 // unrolled fully (see the unroll threshold in the build), so every row index
 // is a constant and the row stays in registers.  On return the solution component r is in
 // sh.sol[gi][r].  Returns false (group-uniform) on a zero or non-finite pivot.
@@ -1125,40 +1172,52 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
         key = take ? ok_ : key;
         kp = take ? op : kp;
       });
-      // the pivot row publishes columns k.. and its RHS
-      if (pos == kp) {
-#pragma unroll
-        for (int j = k; j < NB; ++j) sh.piv[gi][j] = J[j];
-        sh.piv[gi][NB] = rhs;
-      }
-      wave_sync();
-      const TI pv = sh.piv[gi][k];
-      ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
-      const TI rp = recip(pv);
-      // exchange of logical positions k <-> kp
-      if (pos == kp) myrd = rp;
-      if (pos == kp) pos = k;
-      else if (pos == k) pos = kp;
-      if (own && pos > k) {
+      if constexpr (L == 64) {
+        // the pivot row's lane; its columns k.. and RHS are read lane to lane
+        const int pl = wave_lane_of(pos == kp);
+        const TI pv = wave_bcast(J[k], pl);
+        const TI prhs = wave_bcast(rhs, pl);
+        ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
+        const TI rp = recip(pv);
+        if (pos == kp) myrd = rp;
+        if (pos == kp) pos = k;
+        else if (pos == k) pos = kp;
+        const bool upd = own && pos > k;
         const TI l = J[k] * rp;
-        J[k] = l;
+        if (upd) J[k] = l;
 #pragma unroll
-        for (int j = k + 1; j < NB; ++j) J[j] = __builtin_fma(-l, sh.piv[gi][j], J[j]);
-        rhs = __builtin_fma(-l, sh.piv[gi][NB], rhs);
+        for (int j = k + 1; j < NB; ++j) {
+          const TI pj = wave_bcast(J[j], pl);  // read before this step changes any row
+          if (upd) J[j] = __builtin_fma(-l, pj, J[j]);
+        }
+        if (upd) rhs = __builtin_fma(-l, prhs, rhs);
+      } else {
+        // the pivot row publishes columns k.. and its RHS
+        if (pos == kp) {
+#pragma unroll
+          for (int j = k; j < NB; ++j) sh.piv[gi][j] = J[j];
+          sh.piv[gi][NB] = rhs;
+        }
+        wave_sync();
+        const TI pv = sh.piv[gi][k];
+        ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
+        const TI rp = recip(pv);
+        // exchange of logical positions k <-> kp
+        if (pos == kp) myrd = rp;
+        if (pos == kp) pos = k;
+        else if (pos == k) pos = kp;
+        if (own && pos > k) {
+          const TI l = J[k] * rp;
+          J[k] = l;
+#pragma unroll
+          for (int j = k + 1; j < NB; ++j) J[j] = __builtin_fma(-l, sh.piv[gi][j], J[j]);
+          rhs = __builtin_fma(-l, sh.piv[gi][NB], rhs);
+        }
+        wave_sync();
       }
-      wave_sync();
     }
   }
-  // back substitution, column by column from the last
-#pragma unroll
-  for (int k = NB - 1; k >= 0; --k) {
-    if (k < n) {
-      if (pos == k) sh.sol[gi][k] = rhs * myrd;
-      wave_sync();
-      if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
-      wave_sync();
-    }
-  }
+  group_back_substitute<NB, L, TI>(sh, gi, r, n, J, pos, myrd, rhs);
   return ok;
 }
 template <int NB, int L, typename TI>
@@ -1172,6 +1231,7 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
 // Another right-hand side on the factors group_lu_solve kept: step k's pivot
 // row (final position k) publishes its updated RHS, the rows after it apply
 // their multipliers; then the same back substitution.  Solution in sh.sol.
+// (group_back_substitute is defined before group_lu_solve.)
 template <int NB, int L, typename TI>
 __device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
                                                  const TI (&J)[NB], int pos, TI myrd, TI rhs) {
@@ -1179,21 +1239,18 @@ __device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     if (k < n) {
-      if (pos == k) sh.piv[gi][NB] = rhs;
-      wave_sync();
-      if (own && pos > k) rhs = __builtin_fma(-J[k], sh.piv[gi][NB], rhs);
-      wave_sync();
+      if constexpr (L == 64) {
+        const TI rk = wave_bcast(rhs, wave_lane_of(pos == k));
+        if (own && pos > k) rhs = __builtin_fma(-J[k], rk, rhs);
+      } else {
+        if (pos == k) sh.piv[gi][NB] = rhs;
+        wave_sync();
+        if (own && pos > k) rhs = __builtin_fma(-J[k], sh.piv[gi][NB], rhs);
+        wave_sync();
+      }
     }
   }
-#pragma unroll
-  for (int k = NB - 1; k >= 0; --k) {
-    if (k < n) {
-      if (pos == k) sh.sol[gi][k] = rhs * myrd;
-      wave_sync();
-      if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
-      wave_sync();
-    }
-  }
+  group_back_substitute<NB, L, TI>(sh, gi, r, n, J, pos, myrd, rhs);
 }
 
 // Persistent group-mapping kernel.  Each group of L lanes solves one system at
