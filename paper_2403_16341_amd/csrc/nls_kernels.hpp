@@ -1261,8 +1261,17 @@ __device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int
 // the groups that need a new direction, then one residual evaluation for
 // every group holding a trial point; groups diverge freely, and all cross-lane
 // traffic stays inside a group.
+// Minimum resident wavefronts per SIMD asked of the compiler.  The dogleg
+// kernels of the 24 and 32 buckets need a few registers more than two
+// wavefronts can hold; they are held to two at the price of a small spill.
+template <int NB, int ALG> struct GroupMinWaves {
+  static constexpr int value = (ALG == ALG_DOGLEG && (NB == 24 || NB == 32 || NB == 40)) ? 2
+                               : (ALG != ALG_DOGLEG && (NB == 48 || NB == 56)) ? 2 : 1;
+};
+
 template <int NB, int L, int FAM, int ALG, typename TI>
-__global__ __launch_bounds__(64) void k_group(const KArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GroupMinWaves<NB, ALG>::value)))
+void k_group(const KArgs a) {
   constexpr int G = 64 / L;
   constexpr bool HAS_A = RowFam<NB, FAM>::HAS_A;
   __shared__ __attribute__((aligned(16))) GroupShared<NB, L, TI> sh;
