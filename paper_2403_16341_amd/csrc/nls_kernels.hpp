@@ -1261,11 +1261,13 @@ __device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int
 // the groups that need a new direction, then one residual evaluation for
 // every group holding a trial point; groups diverge freely, and all cross-lane
 // traffic stays inside a group.
-// Minimum resident wavefronts per SIMD asked of the compiler.  The dogleg
-// kernels of the 24 and 32 buckets need a few registers more than two
-// wavefronts can hold; they are held to two at the price of a small spill.
+// Minimum resident wavefronts per SIMD asked of the compiler, for the kernels
+// that need a few registers more than that many wavefronts can hold: they
+// are held to it at the price of a small spill (measured faster each time).
 template <int NB, int ALG> struct GroupMinWaves {
-  static constexpr int value = (ALG == ALG_DOGLEG && (NB == 24 || NB == 32 || NB == 40)) ? 2
+  static constexpr int value = (ALG == ALG_DOGLEG && NB == 16) ? 3
+                               : (ALG != ALG_DOGLEG && NB == 24) ? 3
+                               : (ALG == ALG_DOGLEG && (NB == 24 || NB == 32 || NB == 40)) ? 2
                                : (ALG != ALG_DOGLEG && (NB == 48 || NB == 56)) ? 2 : 1;
 };
 
