@@ -76,7 +76,7 @@ extern "C" {
  * the first SUCCESS; if none succeeds, the attempt with the smallest
  * ||F||_inf (the earliest on ties) is returned.  u, fnorm_inf and retcode
  * come from the returned attempt; iters, nfev and njev are totals over the
- * attempts run.  nls_solve_batch only (the request server refuses it).      */
+ * attempts run.  Served by nls_solve_batch and by the request server.       */
 #define NLS_ALG_POLY 3
 /* Sec. 2.1, multi-step scheme of Potra and Ptak: per iteration one Jacobian
  * J_k and two solves, J_k d1 = -F(u_k), y_k = u_k + d1, J_k d2 = -F(y_k),

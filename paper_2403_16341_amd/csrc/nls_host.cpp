@@ -266,6 +266,51 @@ Mapping fixed_mapping(int n) {
   return Mapping{true, n, hipSuccess};
 }
 
+int run_chain(const KArgs& a, bool lane, int key_n, int fam, int prec, const ChainScratch& sc, hipStream_t st) {
+  if (a.count <= 0) return 0;
+  // cnt[stage] = systems handed to the stage, cnt[2 + stage] = its work counter
+  if (int z = launch_zero_counters(sc.cnt, 4, st); z < 0) return z;
+  for (int stage = 0; stage < 2; ++stage) {
+    const int alg = stage == 0 ? ALG_ARMIJO : ALG_DOGLEG;
+    int32_t* const out = stage == 0 ? sc.sel1 : sc.sel2;
+    const int32_t* in = stage == 0 ? a.sys : sc.sel1;
+    const int64_t* in_count = stage == 0 ? nullptr : sc.cnt;
+    if (int z = launch_poly_select(in, in_count, a.count, a.retcode, out, sc.cnt + stage, st); z < 0) return z;
+    KArgs b = a;
+    b.sys = out;
+    b.count_dev = sc.cnt + stage;
+    b.counter = sc.cnt + 2 + stage;
+    b.u_out = sc.u_t;
+    b.fnorm = sc.fnorm_t;
+    b.iters = sc.iters_t;
+    b.retcode = sc.retcode_t;
+    b.nfev = a.nfev ? sc.nfev_t : nullptr;
+    b.njev = a.njev ? sc.njev_t : nullptr;
+    if (int z = launch(key_n, lane, fam, alg, prec, b, st); z != 0) return z;
+    PolyMergeArgs m{};
+    m.list = out;
+    m.count = sc.cnt + stage;
+    m.cap = a.count;
+    m.nsys = a.nsys;
+    m.n = a.n;
+    m.u_off = a.u_off;
+    m.u = a.u_out;
+    m.fnorm = a.fnorm;
+    m.iters = a.iters;
+    m.retcode = a.retcode;
+    m.nfev = a.nfev;
+    m.njev = a.njev;
+    m.u_t = sc.u_t;
+    m.fnorm_t = sc.fnorm_t;
+    m.iters_t = sc.iters_t;
+    m.retcode_t = sc.retcode_t;
+    m.nfev_t = b.nfev;
+    m.njev_t = b.njev;
+    if (int z = launch_poly_merge(m, st); z < 0) return z;
+  }
+  return 0;
+}
+
 }  // namespace rt
 }  // namespace nls
 
@@ -449,19 +494,16 @@ int run_launches(nls_context* c, std::vector<Launch>& L, int prec) {
 }
 
 // The fallback chain of Sec. 3.2 for POLY systems, once the Newton stage has
-// written the results: the systems it left unsolved are gathered on the
-// device, solved again from u0 with Newton + Armijo into scratch outputs and
-// folded into the results; those still unsolved get the dogleg stage.  Every
-// step is a kernel on the context's stream and the host never reads a count.
+// written the results: per segment (one Newton-stage launch), run_chain
+// gathers the systems it left unsolved on the device, solves them again from
+// u0 with Newton + Armijo into scratch outputs, folds the attempt into the
+// results, and gives those still unsolved the dogleg stage.  Every step is a
+// kernel on the context's stream and the host never reads a count.
 int run_poly(nls_context* c, const std::vector<PolySeg>& segs, int prec, DevBuf& db, int64_t M, int64_t utotal) {
   const int ns = (int)segs.size();
   if (ns == 0) return 0;
-  std::vector<int64_t> at(ns);
   int64_t lists = 0;
-  for (int k = 0; k < ns; ++k) {
-    at[k] = lists;
-    lists += segs[k].a.count;
-  }
+  for (auto& g : segs) lists += g.a.count;
   const KArgs& r = segs[0].a;  // every segment writes the same result arrays
   void *sel1, *sel2, *cnt, *ut, *fnt, *itt, *rct, *nft = nullptr, *njt = nullptr;
   hipError_t e;
@@ -474,57 +516,14 @@ int run_poly(nls_context* c, const std::vector<PolySeg>& segs, int prec, DevBuf&
   if ((e = db.alloc(&rct, M * 4)) != hipSuccess) return -(int)e;
   if (r.nfev && (e = db.alloc(&nft, M * 4)) != hipSuccess) return -(int)e;
   if (r.njev && (e = db.alloc(&njt, M * 4)) != hipSuccess) return -(int)e;
-  // per segment k: cnt[4k + stage] = systems handed to the stage,
-  // cnt[4k + 2 + stage] = that stage's work counter
-  int64_t* const cn = (int64_t*)cnt;
-  if (int z = launch_zero_counters(cn, 4 * ns, c->stream); z < 0) return z;
-  for (int stage = 0; stage < 2; ++stage) {
-    const int alg = stage == 0 ? ALG_ARMIJO : ALG_DOGLEG;
-    int32_t* const out = (int32_t*)(stage == 0 ? sel1 : sel2);
-    for (int k = 0; k < ns; ++k) {
-      const KArgs& g = segs[k].a;
-      const int32_t* in = stage == 0 ? g.sys : (const int32_t*)sel1 + at[k];
-      const int64_t* in_count = stage == 0 ? nullptr : cn + 4 * k;
-      int z = launch_poly_select(in, in_count, g.count, r.retcode, out + at[k], cn + 4 * k + stage, c->stream);
-      if (z < 0) return z;
-    }
-    for (int k = 0; k < ns; ++k) {
-      KArgs a = segs[k].a;
-      a.sys = out + at[k];
-      a.count_dev = cn + 4 * k + stage;
-      a.counter = cn + 4 * k + 2 + stage;
-      a.u_out = (double*)ut;
-      a.fnorm = (double*)fnt;
-      a.iters = (int32_t*)itt;
-      a.retcode = (int32_t*)rct;
-      a.nfev = (int32_t*)nft;
-      a.njev = (int32_t*)njt;
-      int z = launch(segs[k].key_n, segs[k].lane, segs[k].fam, alg, prec, a, c->stream);
-      if (z != 0) return z;
-    }
-    for (int k = 0; k < ns; ++k) {
-      const KArgs& g = segs[k].a;
-      PolyMergeArgs m{};
-      m.list = out + at[k];
-      m.count = cn + 4 * k + stage;
-      m.cap = g.count;
-      m.nsys = g.nsys;
-      m.n = g.n;
-      m.u_off = g.u_off;
-      m.u = r.u_out;
-      m.fnorm = r.fnorm;
-      m.iters = r.iters;
-      m.retcode = r.retcode;
-      m.nfev = r.nfev;
-      m.njev = r.njev;
-      m.u_t = (const double*)ut;
-      m.fnorm_t = (const double*)fnt;
-      m.iters_t = (const int32_t*)itt;
-      m.retcode_t = (const int32_t*)rct;
-      m.nfev_t = (const int32_t*)nft;
-      m.njev_t = (const int32_t*)njt;
-      if (int z = launch_poly_merge(m, c->stream); z < 0) return z;
-    }
+  // segments hold disjoint systems, so they share the scratch outputs
+  int64_t at = 0;
+  for (int k = 0; k < ns; ++k) {
+    ChainScratch sc{(int32_t*)sel1 + at, (int32_t*)sel2 + at, (int64_t*)cnt + 4 * k, (double*)ut,
+                    (double*)fnt, (int32_t*)itt, (int32_t*)rct, (int32_t*)nft, (int32_t*)njt};
+    const int z = run_chain(segs[k].a, segs[k].lane, segs[k].key_n, segs[k].fam, prec, sc, c->stream);
+    if (z != 0) return z;
+    at += segs[k].a.count;
   }
   return 0;
 }

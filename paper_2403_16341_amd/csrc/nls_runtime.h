@@ -45,5 +45,25 @@ Mapping fixed_mapping(int n);
 // combination, a negative hipError_t value on a launch failure
 int launch(int n_or_nb, bool lane, int fam, int alg, int prec, const KArgs& a, hipStream_t st);
 
+// Device scratch of one segment of the fallback chain: two system lists of
+// a.count entries, four work counts (zeroed by run_chain), and scratch
+// outputs laid out like the results (u_t over the same offsets as u).
+struct ChainScratch {
+  int32_t* sel1;
+  int32_t* sel2;
+  int64_t* cnt;
+  double* u_t;
+  double* fnorm_t;
+  int32_t* iters_t;
+  int32_t* retcode_t;
+  int32_t* nfev_t;  // may be null when a.nfev is
+  int32_t* njev_t;  // may be null when a.njev is
+};
+// After the Newton-stage launch `a` of a segment (its outputs are the
+// results; a.sys null = systems 0..a.count-1), run the chain's Armijo and
+// dogleg stages on the systems still unsolved, on the same kernel mapping:
+// select, solve from u0 into the scratch outputs, merge, all on stream st.
+int run_chain(const KArgs& a, bool lane, int key_n, int fam, int prec, const ChainScratch& sc, hipStream_t st);
+
 }  // namespace rt
 }  // namespace nls

@@ -152,7 +152,9 @@ int32_t enqueue(nls_server* s, InFlight& L) {
   hipError_t e = hipMemcpyAsync(d, h, g.in_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return NLS_E_DEVICE;
   const Mapping mp = fixed_mapping(q0.n);
-  const int64_t step = slice_systems(q0.n, s->slice_work);
+  const bool chain = q0.alg == ALG_POLY;
+  // (the chain's later stages need the whole launch in one Newton stage)
+  const int64_t step = chain ? std::max<int64_t>(L.plan.m, 1) : slice_systems(q0.n, s->slice_work);
   for (int64_t s0 = 0; s0 < L.plan.m; s0 += step) {
     // one slice: systems s0 .. s0 + cnt - 1 of the launch (its own counter
     // reset; slices on one stream run one after the other)
@@ -174,7 +176,14 @@ int32_t enqueue(nls_server* s, InFlight& L) {
     a.maxiters = q0.b.maxiters;
     a.abstol = q0.b.abstol;
     a.o = to_kopts(q0.opts);
-    if (launch(mp.key_n, mp.lane, q0.fam, q0.alg, q0.b.precision, a, st) != 0) return NLS_E_DEVICE;
+    if (launch(mp.key_n, mp.lane, q0.fam, chain ? ALG_NEWTON : q0.alg, q0.b.precision, a, st) != 0)
+      return NLS_E_DEVICE;
+    if (chain) {
+      ChainScratch sc{(int32_t*)(d + g.sel1),   (int32_t*)(d + g.sel2),    (int64_t*)(d + g.cnt),
+                      (double*)(d + g.u_t),     (double*)(d + g.fnorm_t),  (int32_t*)(d + g.iters_t),
+                      (int32_t*)(d + g.retcode_t), (int32_t*)(d + g.nfev_t), (int32_t*)(d + g.njev_t)};
+      if (run_chain(a, mp.lane, mp.key_n, q0.fam, q0.b.precision, sc, st) != 0) return NLS_E_DEVICE;
+    }
   }
   e = hipMemcpyAsync(h + g.out_off, d + g.out_off, g.out_bytes, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return NLS_E_DEVICE;
@@ -235,7 +244,7 @@ bool admit(nls_server* s) {
     view.reserve(k);
     for (size_t i = 0; i < k; ++i) {
       const Req& q = s->queue[i];
-      view.push_back(QueuedReq{q.id, q.key, q.M, q.P, q.n, launch_work(q.M, q.n)});
+      view.push_back(QueuedReq{q.id, q.key, q.M, q.P, q.n, launch_work(q.M, q.n), q.alg == ALG_POLY});
     }
   }
   if (view.empty()) return false;
@@ -388,12 +397,11 @@ int nls_server_submit(nls_server* s, const nls_batch* b, const nls_results* r, u
     if ((b->family && b->family[i] != q.fam) || (b->n && b->n[i] != q.n) || (b->alg && b->alg[i] != q.alg))
       return sfail(NLS_E_INVALID, "server requests have one family, size and algorithm");
   }
-  if (q.alg == ALG_POLY) return sfail(NLS_E_INVALID, "the fallback chain runs through nls_solve_batch only");
   q.P = nparams_of(q.fam, q.n);
   q.key = merge_key(q);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return sfail(NLS_E_INVALID, "server is shutting down");
-  if (region_layout(q.M, q.P, q.n).total > s->arena.capacity())
+  if (region_layout(q.M, q.P, q.n, q.alg == ALG_POLY).total > s->arena.capacity())
     return sfail(NLS_E_NOMEM, "request needs more device memory than the server's budget");
   q.id = s->next_id++;
   q.t_submit = s->now_ms();

@@ -79,17 +79,21 @@ class Arena {
 
 // Byte layout of one launch's region: the inputs (parameters, then starting
 // points) and, after them, the outputs in one contiguous span so that each
-// direction is a single copy.
+// direction is a single copy.  A launch of the fallback chain adds the
+// chain's device scratch after the outputs (never copied).
 struct Region {
   uint64_t params, u0, in_bytes;  // inputs: [0, in_bytes)
   uint64_t u, fnorm, iters, retcode, nfev, njev;
   uint64_t out_off, out_bytes;    // outputs: [out_off, out_off + out_bytes)
+  // chain scratch (0 when absent): two system lists, four counts, and
+  // scratch outputs laid out like the outputs
+  uint64_t sel1, sel2, cnt, u_t, fnorm_t, iters_t, retcode_t, nfev_t, njev_t;
   uint64_t total;
 };
 
 inline uint64_t align16(uint64_t x) { return (x + 15) / 16 * 16; }
 
-inline Region region_layout(int64_t m, int P, int n) {
+inline Region region_layout(int64_t m, int P, int n, bool chain = false) {
   Region r{};
   uint64_t o = 0;
   r.params = o;
@@ -111,6 +115,14 @@ inline Region region_layout(int64_t m, int P, int n) {
   r.njev = o;
   o = align16(o + 4ull * m);
   r.out_bytes = o - r.out_off;
+  if (chain) {
+    const uint64_t sizes[9] = {4ull * m, 4ull * m, 32, 8ull * m * n, 8ull * m, 4ull * m, 4ull * m, 4ull * m, 4ull * m};
+    uint64_t* at[9] = {&r.sel1, &r.sel2, &r.cnt, &r.u_t, &r.fnorm_t, &r.iters_t, &r.retcode_t, &r.nfev_t, &r.njev_t};
+    for (int k = 0; k < 9; ++k) {
+      *at[k] = o;
+      o = align16(o + sizes[k]);
+    }
+  }
   r.total = o;
   return r;
 }
@@ -122,7 +134,8 @@ struct QueuedReq {
   std::string key;
   int64_t m;  // systems
   int P, n;
-  double cost;  // estimated work, for stream balancing
+  double cost;         // estimated work, for stream balancing
+  bool chain = false;  // the fallback chain (its region carries scratch)
 };
 
 struct PlannedLaunch {
@@ -131,6 +144,7 @@ struct PlannedLaunch {
   std::vector<int64_t> first;    // first system of each request inside the launch
   int64_t m = 0;
   int P = 0, n = 0;
+  bool chain = false;
   double cost = 0.0;
   Region layout{};
   uint64_t offset = 0;           // placement in the arena
@@ -158,6 +172,7 @@ inline std::vector<PlannedLaunch> plan_admission(const std::vector<QueuedReq>& q
       L.key = r.key;
       L.P = r.P;
       L.n = r.n;
+      L.chain = r.chain;
       at[r.key] = cur.size();
       cur.push_back(L);
       it = at.find(r.key);
@@ -167,7 +182,7 @@ inline std::vector<PlannedLaunch> plan_admission(const std::vector<QueuedReq>& q
     L.first.push_back(L.m);
     L.m += r.m;
     L.cost += r.cost;
-    L.layout = region_layout(L.m, L.P, L.n);
+    L.layout = region_layout(L.m, L.P, L.n, L.chain);
     // can every launch of the prefix be placed at once?  (largest first on a
     // copy of the arena; the same order is used for the real placement)
     std::vector<size_t> ord(cur.size());

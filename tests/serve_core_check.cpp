@@ -115,6 +115,32 @@ static std::vector<QueuedReq> random_queue(std::mt19937_64& rng, int len, int ke
   return q;
 }
 
+static void check_chain_layout() {
+  for (int64_t m : {1, 7, 64, 1000}) {
+    for (int n : {1, 8, 24, 64}) {
+      const int P = n * n + n + 1;
+      const Region a = region_layout(m, P, n), c = region_layout(m, P, n, true);
+      CHECK(a.sel1 == 0 && a.total == a.out_off + a.out_bytes, "no scratch without the chain");
+      CHECK(c.out_off == a.out_off && c.out_bytes == a.out_bytes && c.u == a.u && c.njev == a.njev,
+            "the chain keeps the input/output layout");
+      const uint64_t lo[9] = {c.sel1, c.sel2, c.cnt, c.u_t, c.fnorm_t, c.iters_t, c.retcode_t, c.nfev_t, c.njev_t};
+      const uint64_t sz[9] = {4ull * m, 4ull * m, 32, 8ull * m * n, 8ull * m, 4ull * m, 4ull * m, 4ull * m, 4ull * m};
+      uint64_t prev = c.out_off + c.out_bytes;
+      for (int k = 0; k < 9; ++k) {
+        CHECK(lo[k] >= prev && lo[k] % 16 == 0, "chain span %d after the previous, aligned", k);
+        prev = lo[k] + sz[k];
+      }
+      CHECK(c.total >= prev, "chain scratch inside the region");
+    }
+  }
+  // the planner sizes chain launches with their scratch
+  Arena arena(1 << 20);
+  std::vector<QueuedReq> q = {QueuedReq{1, "chain", 10, 73, 8, 1.0, true}};
+  auto plan = plan_admission(q, arena, 8, 8);
+  CHECK(plan.size() == 1 && plan[0].chain && plan[0].layout.total == region_layout(10, 73, 8, true).total,
+        "chain launch planned with scratch");
+}
+
 static void check_planner() {
   std::mt19937_64 rng(11);
   for (int trial = 0; trial < 400; ++trial) {
@@ -261,6 +287,7 @@ static void check_slices_and_streams() {
 }
 
 int main() {
+  check_chain_layout();
   check_slices_and_streams();
   check_arena();
   check_layout();

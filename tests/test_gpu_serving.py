@@ -150,7 +150,7 @@ def test_server_offsets_empty_and_refusals(nls, requests):
         assert np.array_equal(g[k], r[k])
 
     # refusals: larger than the whole budget, several sizes in one request,
-    # a size outside 1..64, the fallback chain
+    # a size outside 1..64
     small = nls.Server(0, mem_budget_bytes=1 << 16)
     big = inputs.homogeneous(inputs.CUBIC, 8, inputs.ARMIJO, np.zeros((2000, 72)), np.zeros((2000, 8)),
                              1e-10, 10)
@@ -165,11 +165,6 @@ def test_server_offsets_empty_and_refusals(nls, requests):
     c70 = inputs.homogeneous(inputs.CUBIC, 70, inputs.ARMIJO, np.zeros((2, 70 * 71)), np.zeros((2, 70)), 1e-10, 10)
     with pytest.raises(nls.NLSError) as ei:
         srv.submit(c70)
-    assert ei.value.code == nls.E_INVALID
-    # the fallback chain runs through the batch path only
-    chain = inputs.homogeneous(inputs.CUBIC, 4, inputs.POLY, np.zeros((2, 20)), np.zeros((2, 4)), 1e-10, 10)
-    with pytest.raises(nls.NLSError) as ei:
-        srv.submit(chain)
     assert ei.value.code == nls.E_INVALID
     srv.close()
 
@@ -239,3 +234,33 @@ def test_server_potra_ptak_requests_match_the_batch_path(nls):
         assert info["status"] == 0
         assert _same(out, ref[ids[info["id"]]])
     assert all((r["retcode"] == 0).mean() > 0.9 for r in ref)
+
+
+def test_server_fallback_chain_requests_match_the_batch_path(nls):
+    """Fallback-chain requests (lane and group kernels, both families) through
+    the server give bitwise the results of the direct batch path, alone and
+    merged; their regions carry the chain's scratch."""
+    rng = np.random.Generator(np.random.PCG64(4343))
+    batches = []
+    for fam, n, M in ((inputs.TANH, 3, 120), (inputs.TANH, 16, 70), (inputs.CUBIC, 8, 90), (inputs.TANH, 40, 12)):
+        if fam == inputs.CUBIC:
+            p, u0 = inputs.cubic_params(rng, M, n), rng.uniform(-6, 6, (M, n))
+        else:
+            p, u0 = inputs.tanh_params(rng, M, n), rng.uniform(-4, 4, (M, n))
+        batches.append(inputs.homogeneous(fam, n, inputs.POLY, p, u0, 1e-10, 30))
+    ctx = nls.Context(0)
+    ref = [nls.solve_host(ctx, b) for b in batches]
+    ctx.close()
+    srv = nls.Server(0, mem_budget_bytes=64 << 20, streams=2)
+    ids = {}
+    for rep in range(2):
+        for j, b in enumerate(batches):
+            ids[srv.submit(b)] = j
+    done = srv.drain()
+    srv.close()
+    assert len(done) == 2 * len(batches)
+    for info, out in done:
+        assert info["status"] == 0
+        assert _same(out, ref[ids[info["id"]]])
+    # the chain did run past its Newton stage somewhere
+    assert any((r["nfev"] > r["iters"] + 1).any() for r in ref)
