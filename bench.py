@@ -449,8 +449,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (x10) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
-              "(--gpus 1); multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X (--gpus 1); "
+              "sharding a batch over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.leg is None and not args.forms and not args.copy_calibration:
