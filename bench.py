@@ -330,6 +330,8 @@ def run_leg(leg, args, timeout):
            "--serve-payloads", str(args.serve_payloads), "--serve-stream", str(args.serve_stream),
            "--serve-load", ",".join(str(x) for x in args.serve_load),
            "--serve-budget-gib", str(args.serve_budget_gib)]
+    if leg == "headline" and args.parity_file:
+        cmd += ["--parity-file", args.parity_file]
     print("[bench] leg %s: child process, limit %.0f s" % (leg, timeout), file=sys.stderr, flush=True)
     try:
         r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=timeout)
@@ -355,6 +357,11 @@ def headline_leg(nls, args):
     out64, step64, gpu64 = run_form(nls, ctx, db, inputs.PREC_FP64, args.steps, args.warmup)
     rc64 = out64["retcode"].cpu().numpy()
     conv64 = int((rc64 == 0).sum())
+    if args.parity_file:
+        # (after the timed region) the FP64 results, for the comparison with the oracle
+        cnt0, _, _ = run_form(nls, ctx, db, inputs.PREC_FP64, 1, 0, with_counters=True)
+        np.savez(args.parity_file, u=cnt0["u"].cpu().numpy(), retcode=cnt0["retcode"].cpu().numpy(),
+                 iters=cnt0["iters"].cpu().numpy())
     print("[bench] fp64: %.3f ms/step, kernel %.3f ms, %d converged" % (step64 * 1e3, np.mean(gpu64), conv64),
           file=sys.stderr, flush=True)
     out32, step32, gpu32 = run_form(nls, ctx, db, inputs.PREC_FP32_INNER, args.steps, args.warmup)
@@ -417,10 +424,32 @@ def cpu_baseline(args):
     r = oracle.solve_batch(b.family, b.n, b.alg, b.params, b.p_off, b.u0, b.u_off, b.abstol,
                            b.maxiters, nthreads=cores)
     dt = time.perf_counter() - t0
-    return {"value": float((r["retcode"] == 0).sum()) / dt, "unit": "solves/s", "cores": cores,
+    base = {"value": float((r["retcode"] == 0).sum()) / dt, "unit": "solves/s", "cores": cores,
             "kind": "oracle",
             "sample": "all %d systems of the workload, single-threaded FP64 oracle per system on %d "
                       "threads over contiguous chunks (%.2f s)" % (b.M, cores, dt)}
+    return base, r
+
+
+def parity_vs_oracle(r, path):
+    """The headline's FP64 GPU results (saved by the headline leg) against
+    the oracle's on every system: return-code and iteration mismatches, and
+    the relative error of u where both succeed."""
+    try:
+        g = np.load(path)
+    except OSError:
+        return None
+    n = 8
+    M = g["retcode"].size
+    both = (g["retcode"] == 0) & (r["retcode"] == 0)
+    ug, uo = g["u"].reshape(M, n), r["u"].reshape(M, n)
+    rel = np.abs(ug - uo).max(axis=1) / np.maximum(np.abs(uo).max(axis=1), np.finfo(float).tiny)
+    rel = rel[both]
+    return {"systems": int(M), "retcode_mismatches": int((g["retcode"] != r["retcode"]).sum()),
+            "iters_off_by_more_than_1": int((np.abs(g["iters"].astype(np.int64) - r["iters"]) > 1).sum()),
+            "rel_err_u_p50": float(np.median(rel)) if rel.size else None,
+            "rel_err_u_p99": float(np.percentile(rel, 99)) if rel.size else None,
+            "rel_err_u_max": float(rel.max()) if rel.size else None}
 
 
 def main():
@@ -430,6 +459,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--systems", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--parity-file", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-extra", action="store_true", help="skip the tanh N=16 and mixed workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
     ap.add_argument("--serve-payloads", type=int, default=64, help="distinct request payloads")
@@ -457,6 +487,9 @@ def main():
         # orchestrator: never touches the GPU itself; every GPU leg runs in a
         # child process with a time limit, so a failing secondary leg cannot
         # cost the headline line
+        import tempfile
+        if not args.parity_file:
+            args.parity_file = os.path.join(tempfile.gettempdir(), "nls_bench_parity_%d.npz" % os.getpid())
         res = run_leg("headline", args, timeout=400.0)
         if "error" in res:
             print(json.dumps({"metric": "converged solves/s, N=8 1M batch, FP64 vs FP32-inner; serving "
@@ -467,7 +500,10 @@ def main():
         if not args.no_serving:
             res["serving"] = run_leg("serving", args, timeout=165.0)
         if not args.no_cpu_baseline:
-            res["cpu_baseline"] = cpu_baseline(args)
+            res["cpu_baseline"], r_oracle = cpu_baseline(args)
+            res["parity_vs_oracle"] = parity_vs_oracle(r_oracle, args.parity_file)
+        if os.path.exists(args.parity_file):
+            os.remove(args.parity_file)
         print(json.dumps(res), flush=True)
         return
 
