@@ -29,6 +29,7 @@ _SRC = os.path.join(_HERE, "nls_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CUBIC, TANH, ROSENBROCK, PAPER = 0, 1, 2, 3
+SQUARE = 9  # oracle-only family: F_i = u_i^2 - p_i, the worked example of Sec. 2.3
 NEWTON, ARMIJO, DOGLEG, POLY, POTRA_PTAK = 0, 1, 2, 3, 4
 RC_SUCCESS, RC_MAXITERS, RC_SINGULAR, RC_NONFINITE, RC_LINESEARCH_FAILED, RC_TR_COLLAPSED = range(6)
 

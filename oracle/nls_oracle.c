@@ -35,6 +35,7 @@ int or_nparams(int family, int n) {
     case OR_FAM_TANH: return n * n + n + 1;       /* A (row-major), b, beta  */
     case OR_FAM_ROSENBROCK: return n >= 2 ? 0 : -1;
     case OR_FAM_PAPER: return n == 2 ? 3 : -1;    /* (a, b, c)               */
+    case OR_FAM_SQUARE: return n;                 /* p                       */
     default: return -1;
   }
 }
@@ -47,6 +48,7 @@ int or_nparams(int family, int n) {
 /*              Rosenbrock equation of Sec. 2.2.1)                           */
 /*   PAPER      F_1 = (u_1 + a)(u_2^3 - b) + c,  F_2 = sin(u_2 e^{u_1} - 1)  */
 /*              (the residual of the workflow example in Sec. 3)             */
+/*   SQUARE     F_i = u_i^2 - p_i  (the sensitivity example of Sec. 2.3)     */
 /* Order: the j-sum first (j ascending), then the elementwise term, then -b. */
 /* ------------------------------------------------------------------------ */
 void or_residual(int family, int n, const double* p, const double* u, double* F) {
@@ -84,6 +86,10 @@ void or_residual(int family, int n, const double* p, const double* u, double* F)
       double cube = u[1] * u[1] * u[1];
       F[0] = (u[0] + a) * (cube - b) + c;
       F[1] = sin(u[1] * exp(u[0]) - 1.0);
+      break;
+    }
+    case OR_FAM_SQUARE: {
+      for (i = 0; i < n; ++i) F[i] = u[i] * u[i] - p[i];
       break;
     }
     default:
@@ -144,6 +150,10 @@ static void residual_dual(int family, int n, const double* p, const dual* u, dua
       dual cube = dmul(dmul(u[1], u[1]), u[1]);
       F[0] = dadd(dmul(dadd(u[0], a), dsub(cube, b)), c);
       F[1] = dsin(dsub(dmul(u[1], dexp(u[0])), dconst(1.0)));
+      break;
+    }
+    case OR_FAM_SQUARE: {
+      for (i = 0; i < n; ++i) F[i] = dsub(dmul(u[i], u[i]), dconst(p[i]));
       break;
     }
     default:
@@ -207,6 +217,10 @@ static void residual_dual_params(int family, int n, const dual* p, const double*
       dual cube = dconst(u[1] * u[1] * u[1]);
       F[0] = dadd(dmul(dadd(dconst(u[0]), a), dsub(cube, b)), c);
       F[1] = dconst(sin(u[1] * exp(u[0]) - 1.0));
+      break;
+    }
+    case OR_FAM_SQUARE: {
+      for (i = 0; i < n; ++i) F[i] = dsub(dconst(u[i] * u[i]), p[i]);
       break;
     }
     default:

@@ -31,7 +31,9 @@
 extern "C" {
 #endif
 
-enum { OR_FAM_CUBIC = 0, OR_FAM_TANH = 1, OR_FAM_ROSENBROCK = 2, OR_FAM_PAPER = 3 };
+/* OR_FAM_SQUARE (F_i = u_i^2 - p_i, the worked example of Sec. 2.3) exists in
+ * the oracle only, to pin its sensitivities against the paper's closed form */
+enum { OR_FAM_CUBIC = 0, OR_FAM_TANH = 1, OR_FAM_ROSENBROCK = 2, OR_FAM_PAPER = 3, OR_FAM_SQUARE = 9 };
 enum { OR_ALG_NEWTON = 0, OR_ALG_ARMIJO = 1, OR_ALG_DOGLEG = 2, OR_ALG_POLY = 3, OR_ALG_POTRA_PTAK = 4 };
 enum {
   OR_RC_SUCCESS = 0, OR_RC_MAXITERS = 1, OR_RC_SINGULAR = 2, OR_RC_NONFINITE = 3,

@@ -16,7 +16,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nls_oracle.c")
 PINS = ["tests/test_oracle_residual_jacobian.py", "tests/test_oracle_lu.py",
-        "tests/test_oracle_solvers.py", "tests/test_oracle_sensitivity.py"]
+        "tests/test_oracle_solvers.py", "tests/test_oracle_sensitivity.py",
+        "tests/test_oracle_trust_region.py"]
 
 MUTANTS = {
     "cubic coefficient": ("F[i] = (s + 0.1 * cube) - b[i];", "F[i] = (s + 0.2 * cube) - b[i];"),
@@ -43,6 +44,12 @@ MUTANTS = {
     "dogleg tau other root branch": ("(-2.0 * qc) / (qb + sq)", "(2.0 * qc) / (qb + sq)"),
     "cauchy step length": ("tcauchy = ng2 / nJg2;", "tcauchy = ng2 / sqrt(nJg2);"),
     "radius not shrunk": ("Delta = o.tr_shrink * nstep;", "Delta = nstep;"),
+    "radius never expands": ("Delta = fmin(o.tr_expand * Delta, o.tr_delta_max);", "Delta = Delta;"),
+    "radius expansion not capped": ("Delta = fmin(o.tr_expand * Delta, o.tr_delta_max);",
+                                    "Delta = o.tr_expand * Delta;"),
+    "accept threshold eta1 -> 0": ("} else if (rho > o.tr_eta1) {", "} else if (rho > 0.0) {"),
+    "expand threshold eta2 -> eta1": ("if (rho >= o.tr_eta2) {", "if (rho >= o.tr_eta1) {"),
+    "collapse never fires": ("if (Delta < o.tr_collapse * fmax(1.0, unorm)) {", "if (0) {"),
     "predicted reduction sign": ("lin[i] = F[i] + s;", "lin[i] = F[i] - s;"),
     "norm is last component": ("double v = fabs(x[i]); if (v > m) m = v;", "double v = fabs(x[i]); m = v;"),
     "poly restarts from the failed endpoint": ("r = or_solve_one(family, n, chain[a], p, u0, abstol,",
