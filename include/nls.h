@@ -103,7 +103,16 @@ extern "C" {
 #define NLS_RC_NONFINITE 3         /* non-finite residual (Newton / start)    */
 #define NLS_RC_LINESEARCH_FAILED 4 /* no trial passed the Armijo test         */
 #define NLS_RC_TR_COLLAPSED 5      /* trust radius below collapse threshold   */
-#define NLS_RC_INVALID 6           /* never produced after validation         */
+/* NLS_RC_INVALID is never a numerical outcome of a validated system.  The
+ * kernels produce it only as a safeguard that keeps every launch finite:
+ * (a) trip guard -- a system still running after maxiters * (max_halvings +
+ *     1) + 4 main-loop trips ends with RC_INVALID, iters = -1 - k and
+ *     fnorm_inf = the trip count;
+ * (b) group disagreement -- in the group mapping (n > 8, or n <= 8 mapped to
+ *     groups), a lane whose copy of the group's state differed from the
+ *     group leader's marks the system RC_INVALID with iters = -100000.
+ * Neither is expected: the test suite asserts that no system ends with it. */
+#define NLS_RC_INVALID 6           /* safeguard only (see above)              */
 
 /* ---- context ------------------------------------------------------------ */
 typedef struct nls_context nls_context;

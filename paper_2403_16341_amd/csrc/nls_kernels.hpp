@@ -914,6 +914,14 @@ __device__ __forceinline__ void stage_matrix(double (&a)[NB][NB + 2], const doub
   }
 }
 
+// Row of the group's LDS matrix that lane r reads: its own row, or row 0 for
+// the lanes past the bucket (r >= NB, only when the group is wider than the
+// bucket), whose values are never used -- so no lane reads past the matrix.
+template <int NB, int L> __device__ __forceinline__ int lds_row(int r) {
+  if constexpr (L > NB) return r < NB ? r : 0;
+  else return r;
+}
+
 // sum_j a_rj v_j over the NB columns of an LDS row (zeros beyond n), in column
 // order, with 16-byte reads of both operands
 template <int NB>
@@ -956,7 +964,7 @@ template <int NB> struct RowFam<NB, FAM_CUBIC> {
                                              bool own, double xr, double& auxr) const {
     sh.x[gi][r] = own ? xr : 0.0;
     wave_sync();
-    const double s = row_dot<NB>(A.a[gi][r], sh.x[gi]);
+    const double s = row_dot<NB>(A.a[gi][lds_row<NB, L>(r)], sh.x[gi]);
     auxr = 0.0;
     wave_sync();
     return own ? (s + 0.1 * (xr * xr * xr)) - b : 0.0;
@@ -966,7 +974,7 @@ template <int NB> struct RowFam<NB, FAM_CUBIC> {
   __device__ __forceinline__ void jacobian_row(GroupShared<NB, L, TI>& sh, GroupA<NB, L, true>& A, int gi, int r,
                                                bool own, double ur, double, TI (&J)[NB]) const {
     const double diag = cubic_term_deriv(ur);
-    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][r]);
+    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][lds_row<NB, L>(r)]);
 #pragma unroll
     for (int h = 0; h < NB / 2; ++h) {
       const double2 v = a2[h];
@@ -1003,7 +1011,7 @@ template <int NB> struct RowFam<NB, FAM_TANH> {
     auxr = own ? tanh(xr) : 0.0;
     sh.x[gi][r] = auxr;
     wave_sync();
-    const double s = row_dot<NB>(A.a[gi][r], sh.x[gi]);
+    const double s = row_dot<NB>(A.a[gi][lds_row<NB, L>(r)], sh.x[gi]);
     wave_sync();
     return own ? (s + beta * xr) - b : 0.0;
   }
@@ -1013,7 +1021,7 @@ template <int NB> struct RowFam<NB, FAM_TANH> {
                                                bool own, double ur, double auxr, TI (&J)[NB]) const {
     sh.dphi[gi][r] = own ? dtanh_known(dseed(ur), auxr).d : 0.0;
     wave_sync();
-    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][r]);
+    const double2* a2 = reinterpret_cast<const double2*>(A.a[gi][lds_row<NB, L>(r)]);
     const double2* d2 = reinterpret_cast<const double2*>(sh.dphi[gi]);
 #pragma unroll
     for (int h = 0; h < NB / 2; ++h) {
@@ -1335,7 +1343,18 @@ void k_group(const KArgs a) {
     {
       const int lead_st = __shfl(gst, gi * L, 64);
       const int lead_ex = __shfl((int)exhausted, gi * L, 64);
-      split = split || grp_any<L>(gst != lead_st || (int)exhausted != lead_ex);
+      const bool disagree = grp_any<L>(gst != lead_st || (int)exhausted != lead_ex);
+      if (disagree && lead_st == ST_IDLE) {
+        // the leader has already ended system s and written its results while
+        // other lanes had not: those lanes write their components now, and
+        // the system is marked invalid before the group moves on
+        if (own && gst != ST_IDLE) a.u_out[uo + r] = u;
+        if (r == 0) {
+          a.retcode[s] = RC_INVALID;
+          a.iters[s] = -100000;
+        }
+      }
+      split = split || disagree;
       gst = lead_st;
       exhausted = lead_ex != 0;
     }
