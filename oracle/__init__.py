@@ -42,12 +42,18 @@ TRACE_FIELDS = [
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
-# Build variants.  "plain" is the oracle.  "fma" is the same source compiled
-# with multiply-add contraction: a rounding-level perturbation of the same
-# arithmetic, used only to tell which systems are sensitive to rounding.
+# Build variants.  "plain" is the oracle.  The others are rounding-level
+# perturbations of the same arithmetic, used only to tell which systems are
+# sensitive to rounding: "fma" is the source compiled with multiply-add
+# contraction; "jitter1" and "jitter2" scale every step componentwise by
+# 1 +- n 2^-53 (the rounding error of a length-n inner product), in two
+# complementary up/down patterns, so that the whole trajectory is perturbed
+# and not only its start.
 VARIANTS = {
     "plain": ("liboracle.so", []),
     "fma": ("liboracle_fma.so", ["-mfma", "-ffp-contract=fast"]),
+    "jitter1": ("liboracle_jitter1.so", ["-DOR_JITTER=1"]),
+    "jitter2": ("liboracle_jitter2.so", ["-DOR_JITTER=2"]),
 }
 
 
@@ -60,7 +66,8 @@ def build(force: bool = False, variant: str = "plain") -> str:
             and os.path.getmtime(out) >= os.path.getmtime(os.path.join(_HERE, "nls_oracle.h"))):
         return out
     tmp = out + ".tmp%d" % os.getpid()
-    flags = [f for f in CFLAGS if not (extra and f == "-ffp-contract=off")]
+    contract = "-ffp-contract=fast" in extra
+    flags = [f for f in CFLAGS if not (contract and f == "-ffp-contract=off")]
     cmd = ["gcc", *flags, *extra, "-o", tmp, _SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)

@@ -329,6 +329,26 @@ static void row_clear(double* row) {
   for (i = 0; i < OR_TRACE_FIELDS; ++i) row[i] = NAN;
 }
 
+/* Rounding probe (classification builds only, never the oracle itself):
+ * built with OR_JITTER = 1 or 2, every step is scaled componentwise by
+ * 1 +- n 2^-53 (n times the unit roundoff: the size of the rounding error of
+ * an inner product of length n, and so of the solve that made the step), up
+ * or down in a pattern of (iteration, component), so that the whole
+ * trajectory -- not only its start -- carries a perturbation of the size of
+ * the rounding differences between two correct implementations.  A system
+ * whose outcome changes under it is sensitive to the rounding order of its
+ * arithmetic.  In the oracle build this is a no-op. */
+#ifdef OR_JITTER
+static void nudge(int n, double* d, int k) {
+  int i;
+  const double e = ldexp((double)n, -53);
+  for (i = 0; i < n; ++i) d[i] = d[i] * (((k + i + OR_JITTER) & 1) ? 1.0 + e : 1.0 - e);
+}
+#define OR_NUDGE(n, d, k) nudge((n), (d), (k))
+#else
+#define OR_NUDGE(n, d, k) ((void)0)
+#endif
+
 /* Newton direction: J delta = -F (eq. newton_descent).  Returns 0 or singular. */
 static int newton_direction(int family, int n, const double* p, const double* u, const double* F,
                             double* J, double* lu, int32_t* piv, double* delta) {
@@ -483,6 +503,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
       if (newton_direction(family, n, p, u, F, J, lu, piv, delta)) {
         r.retcode = OR_RC_SINGULAR; r.iters = k; goto done;
       }
+      OR_NUDGE(n, delta, k);
       for (i = 0; i < n; ++i) u[i] = u[i] + delta[i];
       or_residual(family, n, p, u, F);
       r.nfev += 1;
@@ -509,6 +530,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
       if (newton_direction(family, n, p, u, F, J, lu, piv, delta)) {
         r.retcode = OR_RC_SINGULAR; r.iters = k; goto done;
       }
+      OR_NUDGE(n, delta, k);
       for (i = 0; i < n; ++i) ut[i] = u[i] + delta[i];
       or_residual(family, n, p, ut, Ft);
       r.nfev += 1;
@@ -520,6 +542,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
       /* the same factors, right-hand side -f(y_k) */
       for (i = 0; i < n; ++i) step[i] = -Ft[i];
       or_lu_solve(n, lu, piv, step);
+      OR_NUDGE(n, step, k + 1);
       for (i = 0; i < n; ++i) u[i] = ut[i] + step[i];
       or_residual(family, n, p, u, F);
       r.nfev += 1;
@@ -546,6 +569,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
       if (newton_direction(family, n, p, u, F, J, lu, piv, delta)) {
         r.retcode = OR_RC_SINGULAR; r.iters = k; goto done;
       }
+      OR_NUDGE(n, delta, k);
       double phi0 = sumsq(n, F);
       double alpha = 1.0;
       int accepted = 0, m;
@@ -646,6 +670,7 @@ or_result or_solve_one(int family, int n, int alg, const double* p, const double
           kind = 2;
         }
       }
+      OR_NUDGE(n, step, k);
       for (i = 0; i < n; ++i) ut[i] = u[i] + step[i];
       or_residual(family, n, p, ut, Ft);
       r.nfev += 1;

@@ -6,6 +6,7 @@ import oracle
 
 REL = 1e-9
 STALLS = (oracle.RC_MAXITERS, oracle.RC_LINESEARCH_FAILED, oracle.RC_TR_COLLAPSED)
+RC_INVALID = 6  # the kernels' safeguard code (never an oracle outcome)
 
 
 def np_residual(family, p, u):
@@ -56,6 +57,17 @@ def _same(b, x, y, s):
     return e <= (REL if x["retcode"][s] == oracle.RC_SUCCESS else 1e-6)
 
 
+# Rounding-level perturbations of the oracle's own run: the source built with
+# multiply-add contraction, u0 moved by one ulp either way, both, and every step
+# scaled by 1 +- n 2^-53 in two complementary patterns (the whole trajectory
+# perturbed, not only its start).
+def probe_runs(b, opts=None):
+    up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
+    return [run_oracle(b, opts, variant="fma"), run_oracle(b, opts, u0=up), run_oracle(b, opts, u0=dn),
+            run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn),
+            run_oracle(b, opts, variant="jitter1"), run_oracle(b, opts, variant="jitter2")]
+
+
 def _poly_attempts_sensitive(b, o, opts):
     """A POLY system's outcome is decided by its attempts: whether a stage
     succeeds decides whether the next one runs, and when all fail the smallest
@@ -68,14 +80,11 @@ def _poly_attempts_sensitive(b, o, opts):
     if idx.size == 0:
         return out
     sub = b.subset(idx)
-    up, dn = np.nextafter(sub.u0, np.inf), np.nextafter(sub.u0, -np.inf)
     running = np.ones(sub.M, dtype=bool)  # the chain reaches this stage
     for alg in (oracle.NEWTON, oracle.ARMIJO, oracle.DOGLEG):
         sub.alg[:] = alg
         base = run_oracle(sub, opts)
-        probes = [run_oracle(sub, opts, variant="fma"), run_oracle(sub, opts, u0=up),
-                  run_oracle(sub, opts, u0=dn), run_oracle(sub, opts, variant="fma", u0=up),
-                  run_oracle(sub, opts, variant="fma", u0=dn)]
+        probes = probe_runs(sub, opts)
         for j in np.nonzero(running)[0]:
             if not all(_same(sub, base, q, j) for q in probes):
                 out[idx[j]] = True
@@ -83,33 +92,90 @@ def _poly_attempts_sensitive(b, o, opts):
     return out
 
 
-def classify(b, g, opts=None, strict_all=False, u_tol="strict"):
+def sensitive_mask(b, opts=None):
+    """(oracle result, probe results, mask of the rounding-sensitive systems)."""
+    o = run_oracle(b, opts)
+    probes = probe_runs(b, opts)
+    sens = np.array([not all(_same(b, o, q, s) for q in probes) for s in range(b.M)], dtype=bool)
+    sens |= _poly_attempts_sensitive(b, o, opts)
+    return o, probes, sens
+
+
+# at most this fraction of a parity batch may be rounding-sensitive
+MAX_SENSITIVE = 0.2
+
+
+def pool_batch(make, M, opts=None, max_sensitive=MAX_SENSITIVE):
+    """Parity batch of M systems drawn from a pool of candidates (make(count)
+    returns a Batch of that many seeded systems; the pool is 2M, doubled up
+    to 16M while too few candidates qualify): the candidates in pool order,
+    skipping rounding-sensitive ones once the batch holds max_sensitive * M of
+    them.  The choice uses the oracle alone, so it is the same for every
+    implementation under test; it keeps the strict bar on at least
+    (1 - max_sensitive) of the batch also where far starts make many
+    trajectories chaotic (local methods on the tanh family)."""
+    count = 2 * M
+    while True:
+        pool = make(count)
+        _, _, sens = sensitive_mask(pool, opts)
+        keep, ns = [], 0
+        for s in range(pool.M):
+            if len(keep) == M:
+                break
+            if sens[s]:
+                if ns >= int(max_sensitive * M):
+                    continue
+                ns += 1
+            keep.append(s)
+        if len(keep) == M or count >= 16 * M:
+            break
+        count *= 2
+    assert len(keep) == M, ("pool too sensitive", pool.M, int(sens.sum()))
+    return pool.subset(np.array(keep))
+
+
+def classify(b, g, opts=None, strict_all=False, u_tol="strict", max_sensitive=MAX_SENSITIVE):
     """Compare GPU results g with the oracle.
 
+    No system may end with the kernels' safeguard code RC_INVALID (trip guard
+    or group disagreement), sensitive or not.
+
     A system is rounding-sensitive when the oracle's own outcome changes under
-    a rounding-level perturbation: the same source built with multiply-add
-    contraction, u0 moved by one ulp either way, or both.  Every other system must meet the
-    strict bar (identical return code, iterations within +-1, relative u error
-    <= 1e-9), except that two runs stalled at the same non-root point (u within
-    1e-6) count as one outcome whichever stop test ended them.
+    a rounding-level perturbation (probe_runs).  Every other system must meet
+    the strict bar (identical return code, iterations within +-1, relative u
+    error <= 1e-9), except that two runs stalled at the same non-root point (u
+    within 1e-6) count as one outcome whichever stop test ended them.
+
+    Caps: at most max_sensitive of the batch may be sensitive.  On the
+    sensitive systems the GPU may differ from the oracle no more often than a
+    perturbed oracle does: its return code (sens_rc_diff), and where both
+    succeed, its root (other_root: farther apart than the forward-error bound
+    below) -- each at most 1.5 times the largest count over the probes, plus 3
+    for the sampling noise of small counts.
 
     u_tol="bound" relaxes the 1e-9 of the strict bar to the forward-error
     bound of the stopping test where that is larger (families whose last step
     comes from far away, e.g. the generalized Rosenbrock from U(0,1) starts).  Sensitive systems must still satisfy the invariants, and where
     both sides succeed, agree within the forward-error bound of the stopping
     test, 2 ||J(u*)^-1||_inf abstol (or have reached another valid root)."""
-    o = run_oracle(b, opts)
-    up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
-    probes = [run_oracle(b, opts, variant="fma"), run_oracle(b, opts, u0=up), run_oracle(b, opts, u0=dn),
-              run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn)]
     M = b.M
-    sens = np.array([not all(_same(b, o, q, s) for q in probes) for s in range(M)], dtype=bool)
-    sens |= _poly_attempts_sensitive(b, o, opts)
+    bad = np.nonzero((g["retcode"] == RC_INVALID) | (g["iters"] < 0))[0]
+    assert bad.size == 0, ("systems ended by a kernel safeguard", bad[:5], g["retcode"][bad[:5]],
+                           g["iters"][bad[:5]])
+    o, probes, sens = sensitive_mask(b, opts)
     if strict_all:
         sens[:] = False
+    probe_rc_diff = max([int((sens & (q["retcode"] != o["retcode"])).sum()) for q in probes] + [0])
     report = dict(M=M, sensitive=int(sens.sum()), success_gpu=int((g["retcode"] == 0).sum()),
                   success_oracle=int((o["retcode"] == 0).sum()), strict_fail=[], sens_rc_diff=0,
-                  other_root=0, same_stall=0, max_rel_strict=0.0)
+                  probe_rc_diff=probe_rc_diff, other_root=0, same_stall=0, max_rel_strict=0.0)
+    fb = {}
+
+    def bound(s):
+        if s not in fb:
+            fb[s] = forward_bound(b, o, s)
+        return fb[s]
+
     for s in range(M):
         gs, os_ = int(g["retcode"][s]), int(o["retcode"][s])
         f_, n, _, p, _ = b.system(s)
@@ -135,6 +201,31 @@ def classify(b, g, opts=None, strict_all=False, u_tol="strict"):
             if gs != os_:
                 report["sens_rc_diff"] += 1
             if gs == os_ == oracle.RC_SUCCESS:
-                if rel_err(b, g["u"], o["u"], s) > forward_bound(b, o, s) + REL:
+                if rel_err(b, g["u"], o["u"], s) > bound(s) + REL:
                     report["other_root"] += 1
+    probe_other = 0
+    for q in probes:
+        both = np.nonzero(sens & (q["retcode"] == oracle.RC_SUCCESS) & (o["retcode"] == oracle.RC_SUCCESS))[0]
+        probe_other = max(probe_other, sum(1 for s in both if rel_err(b, q["u"], o["u"], s) > bound(s) + REL))
+    report["probe_other_root"] = probe_other
+    assert report["sensitive"] <= max(max_sensitive * M, 1), ("too many rounding-sensitive systems", report)
+    assert report["sens_rc_diff"] <= 1.5 * probe_rc_diff + 3, ("return codes of sensitive systems", report)
+    assert report["other_root"] <= 1.5 * probe_other + 3, ("other roots of sensitive systems", report)
     return report, o
+
+
+def grid_batch(fam, n, alg, seed, M=None, maxiters=40):
+    """Parity-grid batch: seeded cubic (u0 ~ U(-3, 3)) or tanh (u0 ~ U(-4, 4))
+    systems of size n, drawn through pool_batch."""
+    from paper_2403_16341_amd import inputs
+    M = M or (70 if n <= 16 else 23)
+
+    def make(count):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        if fam == inputs.CUBIC:
+            p, u0 = inputs.cubic_params(rng, count, n), rng.uniform(-3, 3, (count, n))
+        else:
+            p, u0 = inputs.tanh_params(rng, count, n), rng.uniform(-4, 4, (count, n))
+        return inputs.homogeneous(fam, n, alg, p, u0, 1e-10, maxiters)
+
+    return pool_batch(make, M)

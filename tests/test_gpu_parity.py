@@ -12,7 +12,7 @@ from paper_2403_16341_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-from _helpers import REL, classify, rel_err, run_oracle
+from _helpers import REL, classify, grid_batch, rel_err, run_oracle
 
 
 @pytest.fixture(scope="module")
@@ -35,13 +35,14 @@ def run_gpu(nls, ctx, b, precision=None, opts=None):
     return nls.results_to_numpy(out)
 
 
-def compare(b, g, label, opts=None, max_other_root=0, strict_all=False, u_tol="strict"):
-    """Parity bar on one batch (see _helpers.classify); returns the report."""
+def compare(b, g, label, opts=None, strict_all=False, u_tol="strict"):
+    """Parity bar on one batch (see _helpers.classify: strict bar on every
+    system that is not rounding-sensitive, derived caps on the sensitive ones,
+    no safeguard codes); returns the report."""
     rep, o = classify(b, g, opts=opts, strict_all=strict_all, u_tol=u_tol)
     rep["label"] = label
     print({k: (v[:5] if isinstance(v, list) else v) for k, v in rep.items()}, flush=True)
     assert not rep["strict_fail"], (label, rep["strict_fail"][:5])
-    assert rep["other_root"] <= max_other_root, (label, rep["other_root"])
     return rep
 
 
@@ -53,7 +54,7 @@ def test_workload_parity_fp64(nls, ctx, k, M):
     b = inputs.config(k, M=M)
     print("case: workload %d M=%d" % (k, M), flush=True)
     g = run_gpu(nls, ctx, b)
-    rep = compare(b, g, "workload%d" % k, max_other_root=0 if k < 3 else M // 50)
+    rep = compare(b, g, "workload%d" % k)
     if k in (1, 2):
         assert rep["sensitive"] == 0
 
@@ -62,23 +63,23 @@ def test_workload_parity_fp64(nls, ctx, k, M):
 @pytest.mark.parametrize("alg", [inputs.NEWTON, inputs.ARMIJO, inputs.DOGLEG, inputs.POTRA_PTAK])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 9, 12, 16, 20, 24, 32, 40, 64])
 def test_family_alg_size_grid(nls, ctx, fam, alg, n):
-    rng = np.random.Generator(np.random.PCG64(1000 + 10 * n + fam))
-    M = 70 if n <= 16 else 23
-    if fam == inputs.CUBIC:
-        p = inputs.cubic_params(rng, M, n)
-        u0 = rng.uniform(-3, 3, (M, n))
-    else:
-        p = inputs.tanh_params(rng, M, n)
-        # Potra-Ptak is a local method without globalization: from the far
-        # tanh starts a few trajectories wander long enough that the
-        # kernels' and the oracle's roundings steer them apart beyond what
-        # the one-ulp probes reveal, so it is held to the bar from U(-2, 2)
-        w = 2.0 if alg == inputs.POTRA_PTAK else 4.0
-        u0 = rng.uniform(-w, w, (M, n))
-    b = inputs.homogeneous(fam, n, alg, p, u0, 1e-10, 40)
+    b = grid_batch(fam, n, alg, seed=1000 + 10 * n + fam)
     print("case: fam=%d alg=%d n=%d" % (fam, alg, n), flush=True)
     g = run_gpu(nls, ctx, b)
-    compare(b, g, "fam%d-alg%d-n%d" % (fam, alg, n), max_other_root=M // 10 if fam == inputs.TANH else 0)
+    compare(b, g, "fam%d-alg%d-n%d" % (fam, alg, n))
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+@pytest.mark.parametrize("fam", [inputs.CUBIC, inputs.TANH])
+@pytest.mark.parametrize("alg", [inputs.NEWTON, inputs.ARMIJO, inputs.DOGLEG, inputs.POTRA_PTAK, inputs.POLY])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 9, 12, 16, 20, 24, 32, 40, 64])
+def test_wide_seed_sweep(nls, ctx, seed, fam, alg, n):
+    """The same grid on two more seeds and with the fallback chain: every
+    mapping, family and algorithm under the same bar."""
+    b = grid_batch(fam, n, alg, seed=seed * 100000 + 10 * n + fam)
+    print("case: seed=%d fam=%d alg=%d n=%d" % (seed, fam, alg, n), flush=True)
+    g = run_gpu(nls, ctx, b)
+    compare(b, g, "seed%d-fam%d-alg%d-n%d" % (seed, fam, alg, n))
 
 
 def test_edge_families_and_cases(nls, ctx):
@@ -126,7 +127,7 @@ def test_potra_ptak_mixed_batch_and_counters(nls, ctx):
     # (cubic systems only: the mixed workload's tanh starts are far, see the grid)
     b.alg[(rng.random(b.M) < 0.6) & (b.family == inputs.CUBIC)] = inputs.POTRA_PTAK
     g = run_gpu(nls, ctx, b)
-    compare(b, g, "potra-mixed", max_other_root=b.M // 50)
+    compare(b, g, "potra-mixed")
     pp = b.alg == inputs.POTRA_PTAK
     done = pp & (g["iters"] > 0) & (g["retcode"] != oracle.RC_SINGULAR)
     assert np.array_equal(g["njev"][done], g["iters"][done])
@@ -248,7 +249,7 @@ def test_group_mapping_for_small_systems(nls, monkeypatch):
             b = inputs.config(k, M=M)
             compare(b, run_gpu(nls, c, b), "group-mapped workload %d" % k)
         b = inputs.config(4, M=900)
-        compare(b, run_gpu(nls, c, b), "group-mapped mixed", max_other_root=18)
+        compare(b, run_gpu(nls, c, b), "group-mapped mixed")
     finally:
         c.close()
 
@@ -262,7 +263,7 @@ def test_autotuned_mixed_batch(nls):
         lanes = c.mapping(inputs.TANH, 8, inputs.DOGLEG)
         assert lanes in (1, 16)
         print("autotuned lanes per system (tanh, n=8, dogleg):", lanes, flush=True)
-        compare(b, g1, "autotuned mixed", max_other_root=60)
+        compare(b, g1, "autotuned mixed")
         g2 = run_gpu(nls, c, b)      # same mapping, replayed graph: bitwise equal
         for key in ("u", "iters", "retcode", "fnorm_inf", "nfev", "njev"):
             assert np.array_equal(g1[key], g2[key], equal_nan=True), key

@@ -80,7 +80,6 @@ def test_server_parity_alone_vs_mix(nls, requests):
         print("case: request %d family %d n %d M %d" % (rq.rid, b.family[0], b.n[0], b.M), flush=True)
         rep, _ = classify(b, alone[rq.rid], u_tol="bound" if b.family[0] == inputs.TANH else "strict")
         assert not rep["strict_fail"], (rq.rid, rep["strict_fail"][:5])
-        assert rep["other_root"] <= max(1, b.M // 50), (rq.rid, rep["other_root"])
 
 
 def test_server_budget_and_order(nls, requests):
