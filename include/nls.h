@@ -292,6 +292,34 @@ typedef struct {
  * NLS_E_NOMEM, NLS_E_DEVICE.                                                 */
 int nls_sensitivity_batch(nls_context* c, const nls_sens_batch* b, const nls_sens_results* r, uint64_t* ticket);
 
+/* ---- solve without allocating ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * kernels and results as nls_solve_batch, enqueued on `stream` (a
+ * hipStream_t of the current device; NULL = the null stream) with no
+ * context, no ticket and no allocation: completion is stream-ordered (the
+ * caller synchronises the stream).  The kernels' scratch (work counters, and
+ * for NLS_ALG_POLY the lists of unsolved systems and the outputs of the
+ * chain's later stages) lives in one fixed device array of
+ * NLS_NOALLOC_SCRATCH_BYTES that each device holds until the process ends.
+ *   b : a uniform batch -- one family, size and algorithm for every system,
+ *       packed back to back (family/n/alg NULL or all equal, offsets NULL or
+ *       the packed ones) -- with mem_kind NLS_MEM_DEVICE; r likewise device.
+ *   NLS_ALG_POLY batches hold at most NLS_NOALLOC_MAX_CHAIN_SYSTEMS systems
+ *   and NLS_NOALLOC_MAX_CHAIN_UNKNOWNS unknowns; other algorithms have no
+ *   size limit beyond nls_solve_batch's.
+ * Every call on one device shares that device's scratch and leaves its
+ * contents behind (the kernels clear what must start at zero): calls whose
+ * work overlaps on one device race, so issue them on one stream or
+ * serialise them.  Errors (nothing enqueued): NLS_E_INVALID (as
+ * nls_validate, host memory, or a non-uniform batch), NLS_E_NOMEM (a POLY
+ * batch beyond the limits), NLS_E_DEVICE; the message is in
+ * nls_last_error(NULL).                                                     */
+#define NLS_NOALLOC_MAX_CHAIN_SYSTEMS 65536
+#define NLS_NOALLOC_MAX_CHAIN_UNKNOWNS 1048576
+#define NLS_NOALLOC_SCRATCH_BYTES 10486272
+int nls_solve_batch_noalloc(const nls_batch* b, const nls_results* r, void* stream);
+
 /* Number of float64 parameters of a family at size n, or -1 if invalid.      */
 int nls_nparams(int family, int n);
 

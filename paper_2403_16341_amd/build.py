@@ -40,6 +40,7 @@ SOURCES = [
     ("nls_util.hip", True),
     ("nls_poly.hip", True),
     ("nls_sens.hip", True),
+    ("nls_noalloc.hip", True),
     ("nls_lane_f64.hip", True),
     ("nls_lane_f32.hip", True),
 ] + [("nls_group_%s_nb%d.hip" % (p, nb), True) for p in ("f64", "f32") for nb in GROUP_BUCKETS]

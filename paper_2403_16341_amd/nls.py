@@ -34,7 +34,9 @@ CTX_AUTOTUNE = 2
 EXPORTS = ("nls_create", "nls_destroy", "nls_solve_batch", "nls_query", "nls_validate",
            "nls_last_error", "nls_get_mapping", "nls_nparams", "nls_default_options", "nls_abi_version",
            "nls_server_create", "nls_server_submit", "nls_server_poll", "nls_server_stats_get",
-           "nls_server_destroy", "nls_sensitivity_batch")
+           "nls_server_destroy", "nls_sensitivity_batch", "nls_solve_batch_noalloc")
+# fixed limits of nls_solve_batch_noalloc (include/nls.h)
+NOALLOC_MAX_CHAIN_SYSTEMS, NOALLOC_MAX_CHAIN_UNKNOWNS = 65536, 1048576
 SENS_TANGENT, SENS_ADJOINT = 0, 1
 
 
@@ -161,6 +163,8 @@ def lib() -> ctypes.CDLL:
     L.nls_sensitivity_batch.argtypes = [P, ctypes.POINTER(SensBatch), ctypes.POINTER(SensResults),
                                         ctypes.POINTER(ctypes.c_uint64)]
     L.nls_sensitivity_batch.restype = ctypes.c_int
+    L.nls_solve_batch_noalloc.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Results), P]
+    L.nls_solve_batch_noalloc.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -350,6 +354,32 @@ class DeviceBatch:
                     retcode=torch.empty(self.M, dtype=torch.int32, device=dev),
                     nfev=torch.empty(self.M, dtype=torch.int32, device=dev),
                     njev=torch.empty(self.M, dtype=torch.int32, device=dev))
+
+
+def solve_noalloc(batch: "DeviceBatch", out: dict | None = None, precision: int | None = None, opts=None,
+                  stream: "torch.cuda.Stream | None" = None) -> dict:
+    """Enqueue a uniform DeviceBatch through nls_solve_batch_noalloc on a torch
+    stream (default: the current one) and return the result tensors; the work
+    is stream-ordered, so synchronise the stream before reading them."""
+    if not np.isscalar(batch.family) or batch.p_offset is not None:
+        raise NLSError(E_INVALID, "nls_solve_batch_noalloc takes uniform, packed batches")
+    out = out if out is not None else batch.alloc_results()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    b = Batch()
+    b.count = int(batch.M)
+    b.family_all, b.n_all, b.alg_all = int(batch.family), int(batch.n), int(batch.alg)
+    b.precision = int(batch.precision if precision is None else precision)
+    b.mem_kind = MEM_DEVICE
+    b.maxiters = int(batch.maxiters)
+    b.abstol = float(batch.abstol)
+    b.params, b.u0 = _ptr(batch.params), _ptr(batch.u0)
+    if opts is not None:
+        b.opts = ctypes.pointer(opts)
+    r = Results(*[_ptr(out.get(k)) for k in ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev")])
+    rc = lib().nls_solve_batch_noalloc(ctypes.byref(b), ctypes.byref(r), ctypes.c_void_p(st.cuda_stream))
+    if rc != OK:
+        raise NLSError(rc, last_error(None))
+    return out
 
 
 def results_to_numpy(out: dict) -> dict:

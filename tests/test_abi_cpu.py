@@ -156,3 +156,24 @@ def test_sensitivity_entry_rejects_null_context(nls):
     t = ctypes.c_uint64(0)
     assert L.nls_sensitivity_batch(None, ctypes.byref(b), ctypes.byref(r), ctypes.byref(t)) == nls.E_INVALID
     assert nls.SENS_TANGENT == 0 and nls.SENS_ADJOINT == 1
+
+
+def test_noalloc_entry_validates_before_any_device_work(nls):
+    """nls_solve_batch_noalloc refuses host payloads, mixed batches and
+    fallback-chain batches beyond its fixed scratch without touching a
+    device (this process has none)."""
+    L = nls.lib()
+    r = nls.Results()
+    b, keep = _batch(nls)  # host memory
+    u = np.zeros(64)
+    r.u = r.fnorm_inf = r.iters = r.retcode = u.ctypes.data_as(ctypes.c_void_p)
+    assert L.nls_solve_batch_noalloc(ctypes.byref(b), ctypes.byref(r), None) == nls.E_INVALID
+    assert "device memory" in nls.last_error()
+    b, keep = _batch(nls, mem_kind=nls.MEM_DEVICE)
+    ns = np.array([4, 8, 4, 4], dtype=np.uint8)
+    b.n = ns.ctypes.data_as(ctypes.c_void_p)
+    assert L.nls_solve_batch_noalloc(ctypes.byref(b), ctypes.byref(r), None) == nls.E_INVALID
+    assert "uniform" in nls.last_error()
+    b, keep = _batch(nls, mem_kind=nls.MEM_DEVICE, alg=nls.ALG_POLY, count=nls.NOALLOC_MAX_CHAIN_SYSTEMS + 1)
+    assert L.nls_solve_batch_noalloc(ctypes.byref(b), ctypes.byref(r), None) == nls.E_NOMEM
+    assert "scratch" in nls.last_error()
