@@ -88,12 +88,18 @@ class Batch:
         u_off = np.zeros(idx.size + 1, dtype=np.int64)
         np.cumsum(plen, out=p_off[1:])
         np.cumsum(ulen, out=u_off[1:])
-        params = np.concatenate([self.params[self.p_off[s]:self.p_off[s + 1]] for s in idx]) \
-            if idx.size else np.zeros(0)
-        u0 = np.concatenate([self.u0[self.u_off[s]:self.u_off[s + 1]] for s in idx]) \
-            if idx.size else np.zeros(0)
+        params = _gather(self.params, self.p_off, idx, p_off)
+        u0 = _gather(self.u0, self.u_off, idx, u_off)
         return Batch(fam, n, alg, params, p_off, u0, u_off, self.abstol, self.maxiters,
                      self.precision, self.name + "[subset]")
+
+
+def _gather(arr: np.ndarray, off: np.ndarray, idx: np.ndarray, new_off: np.ndarray) -> np.ndarray:
+    """The spans arr[off[s]:off[s+1]] of the systems idx, back to back (new_off:
+    their prefix offsets)."""
+    lens = off[idx + 1] - off[idx]
+    shift = np.repeat(off[idx] - new_off[:-1], lens)
+    return arr[np.arange(new_off[-1], dtype=np.int64) + shift] if idx.size else np.zeros(0)
 
 
 def homogeneous(family: int, n: int, alg: int, params2d: np.ndarray, u02d: np.ndarray,
