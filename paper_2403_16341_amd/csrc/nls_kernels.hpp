@@ -851,7 +851,7 @@ template <int L, typename F> __device__ __forceinline__ void grp_levels(F&& f) {
   f(std::integral_constant<int, 1>{});
   f(std::integral_constant<int, 2>{});
   f(std::integral_constant<int, 4>{});
-  f(std::integral_constant<int, 8>{});
+  if constexpr (L > 8) f(std::integral_constant<int, 8>{});
   if constexpr (L > 16) f(std::integral_constant<int, 16>{});
   if constexpr (L > 32) f(std::integral_constant<int, 32>{});
 }
@@ -889,6 +889,7 @@ template <int NB, int L, typename TI> struct GroupShared {
   double fv[G][L];       // F at the current iterate (for J^T F)
   double dphi[G][L];     // dual derivative of the column map at the iterate
   TI piv[G][NB + 2];     // pivot row of the current elimination step + RHS
+  int ppos[G];           // the pivot row's logical position
   TI sol[G][L];          // solution of the triangular solves
   TI gv[G][L];           // g = J^T F
 };
@@ -1170,19 +1171,23 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
       // the row in position k wins every tie and keeps a NaN (-> singular);
       // other NaN rows never win: they rank below every number
       const bool nan_at_k = grp_any<L>(pos == k && v != v);
-      TI key = cand ? (v != v ? TI(-1) : __builtin_fabs(v)) : TI(-2);
-      int kp = pos;
-      grp_levels<L>([&](auto mc) {
-        constexpr int M = decltype(mc)::value;
-        const TI ok_ = grp_partner<M, L>(key);
-        const int op = grp_partner<M, L>(kp);
-        const bool take = ok_ > key || (ok_ == key && op < kp);
-        key = take ? ok_ : key;
-        kp = take ? op : kp;
-      });
+      const TI key = cand ? (v != v ? TI(-1) : __builtin_fabs(v)) : TI(-2);
+      // the group's largest key, then the row holding it: usually one lane
+      // does; on a tie the smallest position among them wins
+      const TI mx = grp_max<L>(key);
+      const bool top = key == mx;
+      const unsigned long long tb = __ballot(top);
+      const unsigned long long gm = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << (gi * L));
+      bool owner = top;
+      if (__any(__popcll(tb & gm) > 1)) {
+        int pk = top ? pos : 4 * NB;
+        grp_levels<L>([&](auto mc) { pk = min(pk, grp_partner<decltype(mc)::value, L>(pk)); });
+        owner = top && pos == pk;
+      }
       if constexpr (L == 64) {
         // the pivot row's lane; its columns k.. and RHS are read lane to lane
-        const int pl = wave_lane_of(pos == kp);
+        const int pl = wave_lane_of(owner);
+        const int kp = __builtin_amdgcn_readlane(pos, pl);
         const TI pv = wave_bcast(J[k], pl);
         const TI prhs = wave_bcast(rhs, pl);
         ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
@@ -1200,13 +1205,15 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
         }
         if (upd) rhs = __builtin_fma(-l, prhs, rhs);
       } else {
-        // the pivot row publishes columns k.. and its RHS
-        if (pos == kp) {
+        // the pivot row publishes columns k.., its RHS and its position
+        if (owner) {
 #pragma unroll
           for (int j = k; j < NB; ++j) sh.piv[gi][j] = J[j];
           sh.piv[gi][NB] = rhs;
+          sh.ppos[gi] = pos;
         }
         wave_sync();
+        const int kp = sh.ppos[gi];
         const TI pv = sh.piv[gi][k];
         ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
         const TI rp = recip(pv);

@@ -66,6 +66,8 @@ struct KArgs {
   int32_t maxiters;
   double abstol;
   KOpts o;
+  int32_t rows;         // group kernels of the n <= 16 bucket: rows per lane (1 or 2; 0 = the default)
+  int32_t pad2;
 };
 
 }  // namespace nls
