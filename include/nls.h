@@ -118,12 +118,16 @@ extern "C" {
 typedef struct nls_context nls_context;
 
 #define NLS_CTX_THREADSAFE 1u /* serialise calls on one context with a mutex */
-#define NLS_CTX_AUTOTUNE 2u   /* time lane vs group mapping per (n, family,
-                                 algorithm, precision) on first use and keep
-                                 the faster; NLS_AUTOTUNE_CACHE names a file
-                                 that persists the choices; the environment
-                                 variable NLS_MAPPING=lane|group, read at
-                                 nls_create, fixes the n <= 8 mapping instead */
+#define NLS_CTX_AUTOTUNE 2u   /* time the mappings of each (n <= 16, family,
+                                 algorithm, precision) on first use -- one
+                                 system per lane (n <= 8), per 8-lane group
+                                 with two rows per lane, per 16-lane group --
+                                 and keep the fastest; NLS_AUTOTUNE_CACHE
+                                 names a file that persists the choices; the
+                                 environment variable NLS_MAPPING=lane|group,
+                                 read at nls_create, fixes the n <= 8 mapping
+                                 instead, and NLS_GROUP_ROWS=1 makes one row
+                                 per lane the group default                  */
 
 typedef struct {
   int32_t device;            /* HIP device ordinal                            */
@@ -236,9 +240,11 @@ int nls_validate(const nls_batch* b, int64_t* first_bad);
 const char* nls_last_error(const nls_context* c);
 
 /* Kernel mapping the context uses for a combination: *lanes_per_system = 1
- * (one system per lane) or 16/32/64 (one system per group of that many
- * lanes); 0 if the combination has not been tuned yet under
- * NLS_CTX_AUTOTUNE.  Errors: NLS_E_INVALID.                                 */
+ * (one system per lane), 8 (one system per group of 8 lanes holding two rows
+ * each: n <= 16, dense families, all algorithms but Potra-Ptak) or 16/32/64
+ * (one system per group of that many lanes, one row each); 0 if the
+ * combination has not been tuned yet under NLS_CTX_AUTOTUNE (which chooses
+ * among these for n <= 16).  Errors: NLS_E_INVALID.                          */
 int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precision, int32_t* lanes_per_system);
 
 /* ---- sensitivities at a solution (Sec. 2.3) ------------------------------

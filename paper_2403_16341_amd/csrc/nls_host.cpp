@@ -75,6 +75,15 @@ struct nls_context {
   std::map<int, int> tuned;
   std::string tune_cache_path;
   int forced = 0;  // NLS_MAPPING: 1 = lane, 2 = group for every n <= 8 system
+  // plan of a mixed batch (bucketed system order, offsets, sizes): a grow-only
+  // device buffer and its pinned host mirror, reused by every call (so a call
+  // neither allocates nor waits, and a replayed graph sees the same
+  // pointers); plan_ev marks the end of the last copy out of the mirror
+  char* plan_dev = nullptr;
+  char* plan_host = nullptr;
+  size_t plan_cap = 0;
+  hipEvent_t plan_ev = nullptr;
+  bool plan_ev_pending = false;
 };
 
 namespace {
@@ -370,57 +379,88 @@ void load_tuning(nls_context* c) {
   if (FILE* f = std::fopen(c->tune_cache_path.c_str(), "r")) {
     int k = 0, v = 0;
     while (std::fscanf(f, "%d %d", &k, &v) == 2)
-      if (v == 1 || v == 2) c->tuned[k] = v;
+      if (v >= 1 && v <= 4) c->tuned[k] = v;
     std::fclose(f);
   }
 }
 
-// Kernel mapping for a bucket.  Without NLS_CTX_AUTOTUNE (or for n > 8, where
-// only the group mapping exists) the choice is fixed: one system per lane for
-// n <= 8, else one system per 16/32/64-lane group.  With it, the first batch
-// that holds the combination times both mappings on up to 4096 of its systems
-// (results land in the output buffers and are overwritten by the real solve)
-// and the faster one is kept for the life of the context (and in the file named
-// by NLS_AUTOTUNE_CACHE), so the mapping never depends on batch composition.
+// NLS_GROUP_ROWS as the group kernels read it (1 = one row per lane)
+static int group_rows_env() {
+  const char* e = std::getenv("NLS_GROUP_ROWS");
+  return e ? std::atoi(e) : 0;
+}
+
+// Whether the two-rows-per-lane group kernels exist for a combination (the
+// n <= 16 bucket; dense families; Newton, Armijo, dogleg, and the chain,
+// whose stages are those three).
+static bool two_rows_ok(int n, int fam, int alg) {
+  return n <= 16 && (fam == FAM_CUBIC || fam == FAM_TANH) && alg != ALG_POTRA;
+}
+
+// Kernel mapping for a bucket.  Without NLS_CTX_AUTOTUNE the choice is fixed:
+// one system per lane for n <= 8, else one system per group (8 lanes with two
+// rows each up to n = 16 where those kernels exist, else 16/32/64 lanes with
+// one row each).  With it, the first batch that holds the combination times
+// every mapping with a kernel for it -- one system per lane; per group of 8
+// lanes with two rows each; per group of 16 lanes with one row each -- on up
+// to 32,768 of its systems (results land in the output buffers and are
+// overwritten by the real solve), and keeps the fastest for the life of the
+// context (and in the file named by NLS_AUTOTUNE_CACHE), so the mapping never
+// depends on batch composition.
 Mapping choose_mapping(nls_context* c, int n, int fam, int alg, int prec, KArgs a, int64_t P, int64_t count,
                        const int32_t* sys, const int64_t* p_off) {
-  const Mapping lane{true, n, hipSuccess};
-  const Mapping group{false, group_bucket(n), hipSuccess};
-  if (n > 8) return group;
-  if (fam == FAM_PAPER || (fam == FAM_ROSENBROCK && n < 2)) return lane;
-  if (c->forced) return c->forced == 1 ? lane : group;
-  if (!(c->flags & NLS_CTX_AUTOTUNE)) return lane;
+  const Mapping lane{true, n, hipSuccess, 0};
+  const Mapping group{false, group_bucket(n), hipSuccess, 0};
+  const Mapping one{false, group_bucket(n), hipSuccess, 1};
+  const Mapping two{false, group_bucket(n), hipSuccess, 2};
+  const bool rows2 = two_rows_ok(n, fam, alg);
+  // tuned codes: 1 lane, 2 group (default rows), 3 one row per lane, 4 two rows per lane
+  auto of = [&](int v) { return v == 1 ? lane : (v == 3 ? one : (v == 4 && rows2 ? two : group)); };
+  if (n > 16) return group;
+  const bool lane_ok = n <= 8 && !(fam == FAM_ROSENBROCK && n < 2);
+  if (n <= 8 && (fam == FAM_PAPER || (fam == FAM_ROSENBROCK && n < 2))) return lane;
+  if (n <= 8 && c->forced) return c->forced == 1 ? lane : group;
+  if (!(c->flags & NLS_CTX_AUTOTUNE)) return n <= 8 ? lane : group;
+  if (!lane_ok && !rows2) return group;
   const int key = tune_key(n, fam, alg, prec);
   auto it = c->tuned.find(key);
-  if (it != c->tuned.end()) return it->second == 1 ? lane : group;
-  a.count = count < 4096 ? count : 4096;
+  if (it != c->tuned.end()) return of(it->second);
+  // a sample large enough to fill the device with every candidate (the
+  // two-row groups hold eight systems per wavefront), so the timing reflects
+  // throughput and not the parallelism of a small sample
+  a.count = count < 32768 ? count : 32768;
   a.P = P;
-  a.n = n;
   a.sys = sys;
   a.p_off = p_off;
   a.counter = nullptr;
-  float best_ms[2] = {0.f, 0.f};
+  const int codes[3] = {1, 4, 3};
+  float ms[3] = {0.f, 0.f, 0.f};
   hipEvent_t e0, e1;
   hipError_t e;
-  if ((e = hipEventCreate(&e0)) != hipSuccess) return Mapping{true, n, e};
-  if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return Mapping{true, n, e}; }
-  for (int cand = 0; cand < 2; ++cand) {
-    const Mapping mp = cand == 0 ? lane : group;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return Mapping{true, n, e, 0};
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return Mapping{true, n, e, 0}; }
+  int best = -1;
+  for (int cand = 0; cand < 3; ++cand) {
+    if ((cand == 0 && !lane_ok) || (cand == 1 && !rows2)) continue;
+    const Mapping mp = of(codes[cand]);
+    KArgs t = a;
+    t.n = n;
+    t.rows = mp.rows;
     for (int rep = 0; rep < 2; ++rep) {  // the first run loads the code object
       hipEventRecord(e0, c->stream);
-      int rc = launch(mp.key_n, mp.lane, fam, alg, prec, a, c->stream);
+      int rc = launch(mp.key_n, mp.lane, fam, alg, prec, t, c->stream);
       hipEventRecord(e1, c->stream);
-      if (rc < 0) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, (hipError_t)(-rc)}; }
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, e}; }
-      hipEventElapsedTime(&best_ms[cand], e0, e1);
+      if (rc < 0) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, (hipError_t)(-rc), 0}; }
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return Mapping{true, n, e, 0}; }
+      hipEventElapsedTime(&ms[cand], e0, e1);
     }
+    if (best < 0 || ms[cand] < ms[best]) best = cand;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  const int choice = best_ms[0] <= best_ms[1] ? 1 : 2;
-  c->tuned[key] = choice;
-  save_tuning(c, key, choice);
-  return choice == 1 ? lane : group;
+  c->tuned[key] = codes[best];
+  save_tuning(c, key, codes[best]);
+  return of(codes[best]);
 }
 
 // Run a list of persistent launches.  One launch goes straight onto the
@@ -541,13 +581,21 @@ int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precis
   if (!supported(family, n) || alg < 0 || alg >= ALG_KEYS || (precision != 0 && precision != 1))
     return fail(nullptr, NLS_E_INVALID, "nls_get_mapping: bad combination");
   if (alg == ALG_POLY) alg = ALG_NEWTON;  // every stage of the chain runs on the Newton stage's mapping
-  const int group_l = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
-  if (n > 8) { *lanes_per_system = group_l; return NLS_OK; }
-  if (family == FAM_PAPER) { *lanes_per_system = 1; return NLS_OK; }
-  if (c->forced) { *lanes_per_system = c->forced == 1 ? 1 : 16; return NLS_OK; }
-  if (!(c->flags & NLS_CTX_AUTOTUNE)) { *lanes_per_system = 1; return NLS_OK; }
+  const bool rows2 = two_rows_ok(n, family, alg);
+  // lanes per system of the group mapping with its default rows per lane (two
+  // in the FP64 form, one in the FP32-inner form, unless NLS_GROUP_ROWS says)
+  const int env_rows = group_rows_env();
+  const int def_rows = (env_rows == 1 || env_rows == 2) ? env_rows : (precision == NLS_PREC_FP64 ? 2 : 1);
+  const int group_l = n <= 16 ? (rows2 && def_rows == 2 ? 8 : 16) : (n <= 32 ? 32 : 64);
+  if (n > 16) { *lanes_per_system = group_l; return NLS_OK; }
+  if (n <= 8 && (family == FAM_PAPER || (family == FAM_ROSENBROCK && n < 2))) { *lanes_per_system = 1; return NLS_OK; }
+  if (n <= 8 && c->forced) { *lanes_per_system = c->forced == 1 ? 1 : group_l; return NLS_OK; }
+  if (!(c->flags & NLS_CTX_AUTOTUNE)) { *lanes_per_system = n <= 8 ? 1 : group_l; return NLS_OK; }
+  if (!(n <= 8 && !(family == FAM_ROSENBROCK && n < 2)) && !rows2) { *lanes_per_system = group_l; return NLS_OK; }
   auto it = c->tuned.find(tune_key(n, family, alg, precision));
-  *lanes_per_system = it == c->tuned.end() ? 0 : (it->second == 1 ? 1 : 16);
+  if (it == c->tuned.end()) { *lanes_per_system = 0; return NLS_OK; }
+  const int v = it->second;
+  *lanes_per_system = v == 1 ? 1 : (v == 3 ? 16 : (v == 4 ? 8 : group_l));
   return NLS_OK;
 }
 
@@ -595,6 +643,7 @@ int nls_create(const nls_context_desc* d, nls_context** out) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev[j], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->plan_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     nls_destroy(c);
     return hip_fail(nullptr, e, "nls_create");
@@ -628,6 +677,9 @@ int nls_destroy(nls_context* c) {
   }
   if (c->fork_ev) hipEventDestroy(c->fork_ev);
   if (c->counters) hipFree(c->counters);
+  if (c->plan_dev) hipFree(c->plan_dev);
+  if (c->plan_host) hipHostFree(c->plan_host);
+  if (c->plan_ev) hipEventDestroy(c->plan_ev);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
   return NLS_OK;
@@ -762,6 +814,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     a.P = P0;
     a.n = n0;
     a.counter = c->counters;
+    a.rows = mp.rows;
     int rcode = launch(mp.key_n, mp.lane, fam0, alg1, b->precision, a, c->stream);
     if (rcode < 0) return bail((hipError_t)(-rcode), "kernel launch");
     if (rcode > 0) return fail(c, NLS_E_INVALID, "no kernel for this family/size/algorithm");
@@ -774,9 +827,36 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
   } else if (M > 0) {
     // Bucket by kernel: counting sort of the systems on a dense key
     // (mapping, size bucket, family, algorithm), one persistent launch per
-    // bucket, all captured in one graph with parallel branches.
-    std::vector<int64_t> poff(M + 1), uoff(M + 1);
-    std::vector<uint8_t> nn(M);
+    // bucket, all captured in one graph with parallel branches.  The plan is
+    // written into the context's pinned mirror and copied to its device
+    // buffer on the stream (no allocation and no wait in the common case).
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_sys = 0, o_po = al(M * 4), o_uo = o_po + al((M + 1) * 8), o_n = o_uo + al((M + 1) * 8);
+    const size_t plan_bytes = o_n + al(M);
+    if (plan_bytes > c->plan_cap) {
+      // grow (rare): earlier calls may still read the old buffers
+      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+      if (c->plan_dev) hipFree(c->plan_dev);
+      if (c->plan_host) hipHostFree(c->plan_host);
+      c->plan_dev = c->plan_host = nullptr;
+      c->plan_cap = 0;
+      c->plan_ev_pending = false;
+      const size_t cap = plan_bytes + plan_bytes / 4;
+      if ((e = hipMalloc((void**)&c->plan_dev, cap)) != hipSuccess) return bail(e, "hipMalloc");
+      if ((e = hipHostMalloc((void**)&c->plan_host, cap, hipHostMallocDefault)) != hipSuccess) {
+        hipFree(c->plan_dev);
+        c->plan_dev = nullptr;
+        return bail(e, "hipHostMalloc");
+      }
+      c->plan_cap = cap;
+    }
+    // the previous call's copy out of the mirror has finished before it is rewritten
+    if (c->plan_ev_pending && (e = hipEventSynchronize(c->plan_ev)) != hipSuccess)
+      return bail(e, "hipEventSynchronize");
+    int32_t* order = reinterpret_cast<int32_t*>(c->plan_host + o_sys);
+    int64_t* poff = reinterpret_cast<int64_t*>(c->plan_host + o_po);
+    int64_t* uoff = reinterpret_cast<int64_t*>(c->plan_host + o_uo);
+    uint8_t* nn = reinterpret_cast<uint8_t*>(c->plan_host + o_n);
     std::vector<uint16_t> key(M);
     int64_t pacc = 0, uacc = 0;
     for (int64_t s = 0; s < M; ++s) {
@@ -796,26 +876,18 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
     std::vector<int64_t> cnt(kCombos + 1, 0);
     for (int64_t s = 0; s < M; ++s) cnt[key[s] + 1]++;
     for (int i = 0; i < kCombos; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> order(M);
     {
       std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
       for (int64_t s = 0; s < M; ++s) order[at[key[s]]++] = (int32_t)s;
     }
-    void *dsys = nullptr, *dpo = nullptr, *duo = nullptr, *dn = nullptr;
-    if ((e = db.alloc(&dsys, M * 4)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = db.alloc(&dpo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = db.alloc(&duo, (M + 1) * 8)) != hipSuccess) return bail(e, "hipMalloc");
-    if ((e = db.alloc(&dn, M)) != hipSuccess) return bail(e, "hipMalloc");
-    // these host vectors die with this call: the copies complete before return
-    if ((e = hipMemcpyAsync(dsys, order.data(), M * 4, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(c->plan_dev, c->plan_host, plan_bytes, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
       return bail(e, "hipMemcpyAsync");
-    if ((e = hipMemcpyAsync(dpo, poff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-      return bail(e, "hipMemcpyAsync");
-    if ((e = hipMemcpyAsync(duo, uoff.data(), (M + 1) * 8, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-      return bail(e, "hipMemcpyAsync");
-    if ((e = hipMemcpyAsync(dn, nn.data(), M, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-      return bail(e, "hipMemcpyAsync");
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+    if ((e = hipEventRecord(c->plan_ev, c->stream)) != hipSuccess) return bail(e, "hipEventRecord");
+    c->plan_ev_pending = true;
+    void* dsys = c->plan_dev + o_sys;
+    void* dpo = c->plan_dev + o_po;
+    void* duo = c->plan_dev + o_uo;
+    void* dn = c->plan_dev + o_n;
     // one launch per kernel: combinations that map to the same group bucket
     // share it (their n rides along in nsys)
     std::vector<Launch> launches;
@@ -836,7 +908,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
       const int alg1 = poly ? ALG_NEWTON : alg;  // the chain starts with Newton
       const Mapping mp = choose_mapping(c, n, fam, alg1, b->precision, a, 0, c1 - c0, a.sys, a.p_off);
       if (mp.error) return bail(mp.error, "autotune");
-      const int kid = (mp.lane ? 0 : 100000) + mp.key_n * 64 + fam * ALG_KEYS + alg;
+      const int kid = (mp.lane ? 0 : 100000 * (1 + mp.rows)) + mp.key_n * 64 + fam * ALG_KEYS + alg;
       auto it = by_kernel.find(kid);
       if (it != by_kernel.end() && !mp.lane && launches[it->second].a.sys + launches[it->second].a.count == a.sys) {
         launches[it->second].a.count += a.count;  // adjacent in the sorted order
@@ -844,6 +916,7 @@ int nls_solve_batch(nls_context* c, const nls_batch* b, const nls_results* r, ui
         continue;
       }
       a.n = mp.key_n;
+      a.rows = mp.rows;
       Launch L{a, mp.lane, mp.key_n, fam, alg1, (double)a.count * n * n * n, poly};
       by_kernel[kid] = launches.size();
       launches.push_back(L);

@@ -34,6 +34,7 @@ struct Mapping {
   bool lane;
   int key_n;  // n for the lane mapping, the size bucket for the group mapping
   hipError_t error;
+  int rows = 0;  // group mapping, n <= 16 bucket: rows per lane (0 = the default, two)
 };
 // size bucket (16, 24, ..., 64) of the group mapping for n > 8
 int group_bucket(int n);
