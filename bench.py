@@ -145,6 +145,9 @@ def extra_workloads(nls, ctx, args):
     from paper_2403_16341_amd import inputs
     import torch
     out = {"cubic_n4_newton_1024": latency_workload(nls, ctx)}
+    # the mixed batch runs on a context that times the mappings of its n <= 8
+    # buckets on first use (lane or group) and keeps the faster
+    tctx = nls.Context(0, flags=nls.CTX_AUTOTUNE)
     for k, name, poly in ((3, "tanh_n16_dogleg_262144", False), (4, "mixed_500000", False),
                           (3, "tanh_n16_poly_262144", True)):
         b = inputs.config(k)
@@ -153,8 +156,9 @@ def extra_workloads(nls, ctx, args):
         db = nls.DeviceBatch(b)
         torch.cuda.synchronize()
         entry = {"systems": b.M}
+        c_ = tctx if k == 4 else ctx
         for prec, pname in ((inputs.PREC_FP64, "fp64"), (inputs.PREC_FP32_INNER, "fp32_inner")):
-            o, step, gms = run_form(nls, ctx, db, prec, 3, 1, with_counters=True)
+            o, step, gms = run_form(nls, c_, db, prec, 5, 1, with_counters=True)
             rc = o["retcode"].cpu().numpy()
             conv = int((rc == 0).sum())
             it = o["iters"].cpu().numpy()
@@ -177,9 +181,17 @@ def extra_workloads(nls, ctx, args):
             entry[pname] = e
             print("[bench] %s %s: %.3f ms/step, %d converged" % (name, pname, step * 1e3, conv),
                   file=sys.stderr, flush=True)
+        if k == 4:
+            # lanes per system chosen for each (n, family, algorithm) of the batch
+            entry["mapping_lanes_per_system"] = {
+                "n%d-%s-%s-%s" % (nn, ("cubic", "tanh")[f], ("newton", "armijo", "dogleg")[a], pn):
+                    tctx.mapping(f, nn, a, pr)
+                for nn in sorted(set(int(x) for x in b.n)) for f in (0, 1) for a in (1, 2)
+                for pr, pn in ((inputs.PREC_FP64, "fp64"), (inputs.PREC_FP32_INNER, "fp32_inner"))}
         out[name] = entry
         del db
         torch.cuda.empty_cache()
+    tctx.close()
     out["tanh_n16_adjoint_262144"] = sensitivity_workload(nls, ctx)
     out["paper_gpu_rosenbrock_n10_1024"] = paper_gpu_workload(nls, ctx)
     out["cubic_n8_potra_ptak_1M"] = potra_ptak_workload(nls, ctx)
@@ -575,12 +587,14 @@ def same_outcome(b, x, y):
 def probe_sensitive(b, threads):
     """Rounding-sensitive systems: the oracle's outcome changes under a
     rounding-level perturbation (multiply-add contraction, u0 moved by one
-    ulp either way, both, or every step scaled by 1 +- n 2^-53)."""
+    ulp either way, both, every step scaled by 1 +- n 2^-53, or sums taken as
+    a balanced tree)."""
     base = oracle_solve(b, threads)
     up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
     probes = [oracle_solve(b, threads, "fma"), oracle_solve(b, threads, u0=up), oracle_solve(b, threads, u0=dn),
               oracle_solve(b, threads, "fma", u0=up), oracle_solve(b, threads, "fma", u0=dn),
-              oracle_solve(b, threads, "jitter1"), oracle_solve(b, threads, "jitter2")]
+              oracle_solve(b, threads, "jitter1"), oracle_solve(b, threads, "jitter2"),
+              oracle_solve(b, threads, "pairwise")]
     ok = np.ones(b.M, dtype=bool)
     for q in probes:
         ok &= same_outcome(b, base, q)
@@ -672,7 +686,8 @@ def main():
     ap.add_argument("--leg", choices=("headline", "extras", "serving", "oracle"), default=None,
                     help="run one leg in this process and print its JSON")
     ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")
-    ap.add_argument("--workload", choices=("headline", "tanh16", "tanh16poly", "adjoint16", "cubic64", "cubic40"),
+    ap.add_argument("--workload", choices=("headline", "tanh16", "tanh16poly", "adjoint16", "cubic64", "cubic40",
+                                           "mixed"),
                     default="headline",
                     help="profiling: the batch --forms times (the headline, 2^18 x N=16 tanh dogleg, the same under "
                          "the fallback chain, adjoint sensitivities of it, or "
@@ -760,6 +775,8 @@ def main():
             b = inputs.config(3)
             if args.workload == "tanh16poly":
                 b.alg[:] = inputs.POLY
+        elif args.workload == "mixed":
+            b = inputs.config(4)
         else:
             nn = 64 if args.workload == "cubic64" else 40
             rng = np.random.Generator(np.random.PCG64(7000 + nn))

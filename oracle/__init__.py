@@ -48,12 +48,14 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 # contraction; "jitter1" and "jitter2" scale every step componentwise by
 # 1 +- n 2^-53 (the rounding error of a length-n inner product), in two
 # complementary up/down patterns, so that the whole trajectory is perturbed
-# and not only its start.
+# and not only its start; "pairwise" adds the merit ||F||^2 and the dogleg's
+# inner products as a balanced tree instead of in index order.
 VARIANTS = {
     "plain": ("liboracle.so", []),
     "fma": ("liboracle_fma.so", ["-mfma", "-ffp-contract=fast"]),
     "jitter1": ("liboracle_jitter1.so", ["-DOR_JITTER=1"]),
     "jitter2": ("liboracle_jitter2.so", ["-DOR_JITTER=2"]),
+    "pairwise": ("liboracle_pairwise.so", ["-DOR_PAIRWISE"]),
 }
 
 

@@ -302,6 +302,7 @@ static double norm_inf(int n, const double* x) {
   for (i = 0; i < n; ++i) { double v = fabs(x[i]); if (v > m) m = v; }
   return m;
 }
+#ifndef OR_PAIRWISE
 static double sumsq(int n, const double* x) {
   double s = 0.0;
   int i;
@@ -314,6 +315,19 @@ static double dot(int n, const double* x, const double* y) {
   for (i = 0; i < n; ++i) s = s + x[i] * y[i];
   return s;
 }
+#else
+/* Rounding probe (classification build only): the same sums added as a
+ * balanced binary tree instead of in index order -- another rounding order of
+ * the merit ||F||^2 and of the dogleg's inner products. */
+static double pw_dot(const double* x, const double* y, int lo, int hi) {
+  int mid;
+  if (hi - lo == 1) return x[lo] * y[lo];
+  mid = lo + (hi - lo) / 2;
+  return pw_dot(x, y, lo, mid) + pw_dot(x, y, mid, hi);
+}
+static double sumsq(int n, const double* x) { return n > 0 ? pw_dot(x, x, 0, n) : 0.0; }
+static double dot(int n, const double* x, const double* y) { return n > 0 ? pw_dot(x, y, 0, n) : 0.0; }
+#endif
 /* the reported residual norm: +inf when the residual is not finite */
 static double report_norm(int n, const double* F) {
   return all_finite(n, F) ? norm_inf(n, F) : INFINITY;

@@ -58,14 +58,16 @@ def _same(b, x, y, s):
 
 
 # Rounding-level perturbations of the oracle's own run: the source built with
-# multiply-add contraction, u0 moved by one ulp either way, both, and every step
+# multiply-add contraction, u0 moved by one ulp either way, both, every step
 # scaled by 1 +- n 2^-53 in two complementary patterns (the whole trajectory
-# perturbed, not only its start).
+# perturbed, not only its start), and the merit and inner products summed as a
+# balanced tree (the rounding order of a butterfly reduction).
 def probe_runs(b, opts=None):
     up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
     return [run_oracle(b, opts, variant="fma"), run_oracle(b, opts, u0=up), run_oracle(b, opts, u0=dn),
             run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn),
-            run_oracle(b, opts, variant="jitter1"), run_oracle(b, opts, variant="jitter2")]
+            run_oracle(b, opts, variant="jitter1"), run_oracle(b, opts, variant="jitter2"),
+            run_oracle(b, opts, variant="pairwise")]
 
 
 def _poly_attempts_sensitive(b, o, opts):

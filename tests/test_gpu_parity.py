@@ -239,12 +239,13 @@ def test_full_size_headline_sampled(nls, ctx):
 
 
 def test_group_mapping_for_small_systems(nls, monkeypatch):
-    """The 16-lane group kernels also solve n <= 8 systems (the autotuner's
-    alternative); forced through NLS_MAPPING, they meet the same bar."""
+    """The group kernels of the n <= 16 bucket also solve n <= 8 systems (the
+    autotuner's alternatives); forced through NLS_MAPPING, they meet the same
+    bar."""
     monkeypatch.setenv("NLS_MAPPING", "group")
     c = nls.Context(0)
     try:
-        assert c.mapping(inputs.CUBIC, 8, inputs.ARMIJO) == 16
+        assert c.mapping(inputs.CUBIC, 8, inputs.ARMIJO) == 8
         for k, M in ((1, 300), (2, 333)):
             b = inputs.config(k, M=M)
             compare(b, run_gpu(nls, c, b), "group-mapped workload %d" % k)
@@ -261,7 +262,8 @@ def test_autotuned_mixed_batch(nls):
         assert c.mapping(inputs.TANH, 8, inputs.DOGLEG) == 0   # not tuned yet
         g1 = run_gpu(nls, c, b)
         lanes = c.mapping(inputs.TANH, 8, inputs.DOGLEG)
-        assert lanes in (1, 16)
+        assert lanes in (1, 8, 16)
+        assert c.mapping(inputs.TANH, 12, inputs.DOGLEG) in (8, 16)
         print("autotuned lanes per system (tanh, n=8, dogleg):", lanes, flush=True)
         compare(b, g1, "autotuned mixed")
         g2 = run_gpu(nls, c, b)      # same mapping, replayed graph: bitwise equal
@@ -318,3 +320,26 @@ def test_fp32_inner_grid(nls, ctx, fam, alg, n):
         assert errs.max() <= 1e-8, errs.max()
     else:
         assert (errs <= 1e-8).sum() >= 0.8 * both.sum(), ((errs <= 1e-8).sum(), both.sum())
+
+
+@pytest.mark.parametrize("n", [9, 16])
+@pytest.mark.parametrize("rows", [1, 2])
+def test_group_rows_per_lane(nls, monkeypatch, n, rows):
+    """Systems of 9..16 unknowns run on groups of 8 lanes with two rows per
+    lane (the FP64 default) or of 16 lanes with one row per lane (the
+    FP32-inner default); NLS_GROUP_ROWS forces either, and both meet the bar
+    in both forms."""
+    monkeypatch.setenv("NLS_GROUP_ROWS", str(rows))
+    c = nls.Context(0)
+    try:
+        for fam in (inputs.CUBIC, inputs.TANH):
+            for alg in (inputs.NEWTON, inputs.ARMIJO, inputs.DOGLEG):
+                b = grid_batch(fam, n, alg, seed=8000 + 10 * n + fam + 100 * alg)
+                print("case: rows=%d fam=%d alg=%d n=%d" % (rows, fam, alg, n), flush=True)
+                compare(b, run_gpu(nls, c, b), "rows%d-fam%d-alg%d-n%d" % (rows, fam, alg, n))
+                g32 = run_gpu(nls, c, b, precision=inputs.PREC_FP32_INNER)
+                assert (g32["retcode"] != nls.RC_INVALID).all()
+                succ = g32["retcode"] == oracle.RC_SUCCESS
+                assert (g32["fnorm_inf"][succ] <= b.abstol).all()
+    finally:
+        c.close()
