@@ -584,17 +584,32 @@ def same_outcome(b, x, y):
     return ok & ((fin & (rel <= tol)) | (~fin & (x["retcode"] == 3)))
 
 
+def _few_ulp_start(u0, seed):
+    """u0 with every component scaled by 1 + k 2^-52, k in {-4, ..., 4}
+    hashed from the component's bits and the seed (the same map the tests
+    use, so a system gets the same probes in any batch)."""
+    bits = np.ascontiguousarray(u0, dtype=np.float64).view(np.uint64)
+    h = (bits ^ np.uint64((seed * 0x632BE59BD9B4E019) & 0xFFFFFFFFFFFFFFFF)) * np.uint64(0x9E3779B97F4A7C15)
+    k = ((h >> np.uint64(40)) % np.uint64(9)).astype(np.int64) - 4
+    return u0 * (1.0 + k * 2.0 ** -52)
+
+
 def probe_sensitive(b, threads):
     """Rounding-sensitive systems: the oracle's outcome changes under a
     rounding-level perturbation (multiply-add contraction, u0 moved by one
-    ulp either way, both, every step scaled by 1 +- n 2^-53, or sums taken as
-    a balanced tree)."""
+    ulp either way, both, every step scaled by 1 +- n 2^-53, sums taken as a
+    balanced tree, or u0 moved a few ulps in 18 pseudo-random directions)."""
     base = oracle_solve(b, threads)
     up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
     probes = [oracle_solve(b, threads, "fma"), oracle_solve(b, threads, u0=up), oracle_solve(b, threads, u0=dn),
               oracle_solve(b, threads, "fma", u0=up), oracle_solve(b, threads, "fma", u0=dn),
               oracle_solve(b, threads, "jitter1"), oracle_solve(b, threads, "jitter2"),
               oracle_solve(b, threads, "pairwise")]
+    for seed in range(1, 19):
+        # a start a few ulps from u0 in a direction hashed from the bits of u0
+        # (seeds 1 and 2 are the tests' two; this runs on the mismatched
+        # systems only, so it affords 16 more)
+        probes.append(oracle_solve(b, threads, u0=_few_ulp_start(b.u0, seed)))
     ok = np.ones(b.M, dtype=bool)
     for q in probes:
         ok &= same_outcome(b, base, q)

@@ -60,14 +60,29 @@ def _same(b, x, y, s):
 # Rounding-level perturbations of the oracle's own run: the source built with
 # multiply-add contraction, u0 moved by one ulp either way, both, every step
 # scaled by 1 +- n 2^-53 in two complementary patterns (the whole trajectory
-# perturbed, not only its start), and the merit and inner products summed as a
-# balanced tree (the rounding order of a butterfly reduction).
+# perturbed, not only its start), the merit and inner products summed as a
+# balanced tree (the rounding order of a butterfly reduction), and two starts a
+# few ulps from u0 in random directions.
+def probe_starts(u0, seeds=(1, 2)):
+    """Starting points a few ulps from u0: every component scaled by
+    1 + k 2^-52, k in {-4, ..., 4} hashed from the component's own bits and
+    the seed, so a system gets the same probes in any batch it sits in."""
+    bits = np.ascontiguousarray(u0, dtype=np.float64).view(np.uint64)
+    out = []
+    for seed in seeds:
+        h = (bits ^ np.uint64((seed * 0x632BE59BD9B4E019) & 0xFFFFFFFFFFFFFFFF)) * np.uint64(0x9E3779B97F4A7C15)
+        k = ((h >> np.uint64(40)) % np.uint64(9)).astype(np.int64) - 4
+        out.append(u0 * (1.0 + k * 2.0 ** -52))
+    return out
+
+
 def probe_runs(b, opts=None):
     up, dn = np.nextafter(b.u0, np.inf), np.nextafter(b.u0, -np.inf)
+    r1, r2 = probe_starts(b.u0)
     return [run_oracle(b, opts, variant="fma"), run_oracle(b, opts, u0=up), run_oracle(b, opts, u0=dn),
             run_oracle(b, opts, variant="fma", u0=up), run_oracle(b, opts, variant="fma", u0=dn),
             run_oracle(b, opts, variant="jitter1"), run_oracle(b, opts, variant="jitter2"),
-            run_oracle(b, opts, variant="pairwise")]
+            run_oracle(b, opts, variant="pairwise"), run_oracle(b, opts, u0=r1), run_oracle(b, opts, u0=r2)]
 
 
 def _poly_attempts_sensitive(b, o, opts):
