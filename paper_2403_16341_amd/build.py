@@ -30,7 +30,11 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-ffp-contract=fast",
           # the group kernels unroll their LU fully up to n = 64 (row arrays in
           # registers); the default limit for requested unrolling stops at 40
-          "-mllvm", "-pragma-unroll-threshold=1000000"]
+          "-mllvm", "-pragma-unroll-threshold=1000000",
+          # atomics here are issued by one lane for its wavefront; the
+          # compiler's cross-lane rewrite would wait for each result at once
+          # instead of where it is used
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 GROUP_BUCKETS = (16, 24, 32, 40, 48, 56, 64)
 SOURCES = [

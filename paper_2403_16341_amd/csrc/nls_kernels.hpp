@@ -39,6 +39,10 @@ __device__ __forceinline__ bool finite64(double x) { return __builtin_isfinite(x
 __device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
 template <typename T> __device__ __forceinline__ bool fin(T x) { return __builtin_isfinite(x); }
 
+// s_waitcnt operands (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8; a field at its maximum does not wait)
+enum : int { WAITCNT_VM0 = 0x0F70, WAITCNT_LGKM0 = 0xC07F };
+
 // Wave-level ordering point for LDS traffic between lanes of one wavefront
 // (every workgroup here is a single wave, so no s_barrier is needed).
 __device__ __forceinline__ void wave_sync() {
@@ -493,24 +497,37 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
   const DoglegOpts o = a.o.dogleg();
   const int64_t trip_cap = trip_limit(maxit, mh);
 
-  // chunk currently being handed out (wave-uniform): from the device-wide
-  // counter when there is one, else blockIdx.x, blockIdx.x + gridDim.x, ...
-  auto next_chunk = [&](int64_t cur) -> int64_t {
-    if (!a.counter) return cur + gridDim.x;
+  // Chunk currently being handed out (wave-uniform).  Without a device-wide
+  // counter: blockIdx.x, blockIdx.x + gridDim.x, ...  With one, the first
+  // three quarters of each wavefront's fair share of chunks are assigned the
+  // same way and only the rest come from the counter: dynamic assignment
+  // still balances the end of the launch, while most hand-outs skip the
+  // atomic's round trip (its result is needed at once).
+  const int64_t nstatic = a.counter ? (nchunks / gridDim.x) * 3 / 4 : INT64_MAX;
+  int64_t taken = 0;  // chunks this wavefront has taken
+  auto next_chunk = [&]() -> int64_t {
+    const int64_t t = taken++;
+    if (t < nstatic) return (int64_t)blockIdx.x + t * gridDim.x;
     int64_t c = 0;
     if (lane == 0) c = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(a.counter), 1ull);
-    return __shfl(c, 0, 64);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)c >> 32));
+    return nstatic * gridDim.x + (int64_t)(((uint64_t)hi << 32) | lo);
   };
-  int64_t chunk = a.counter ? next_chunk(0) : (int64_t)blockIdx.x;
+  int64_t chunk = next_chunk();
   int buf_next = 0, buf_cnt = 0;
-  bool buf_wait = false;
   if (chunk < nchunks) {
     buf_cnt = (int)min<int64_t>(64, count - chunk * 64);
-    if (staged) {
-      stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
-      buf_wait = true;
-    }
+    if (staged) stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
   }
+  // The first copy completes before the loop.  Each later copy is issued in a
+  // trip's refill and waited for in the middle of that trip, ahead of the
+  // trip's result stores: a wait on the vector-memory counter cannot tell
+  // loads from stores, so a wait at the next refill would also wait for the
+  // stores just issued.  With no copy in flight at the loop head, the LDS
+  // reads of the refill need no wait on the vector-memory counter.
+  __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
+  wave_sync();
 
   // per-lane state
   int st = ST_IDLE;
@@ -543,11 +560,6 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
     // ---------------- retire / refill ----------------
     const bool more = chunk < nchunks;
     if (__any(st == ST_IDLE) && more) {
-      if (buf_wait) {
-        __builtin_amdgcn_s_waitcnt(0);
-        wave_sync();
-        buf_wait = false;
-      }
       const unsigned long long idle = __ballot(st == ST_IDLE);
       const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
@@ -556,33 +568,35 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       if (fresh) {
         const int slot = buf_next + rank;
         const int64_t t = chunk * 64 + slot;
-        s = a.sys ? (int64_t)a.sys[t] : t;
-        uo = a.u_off ? a.u_off[s] : s * N;
         if (staged) {
+          // packed and uniform: no index lookups
+          s = t;
+          uo = t * N;
           double pv[PS];
           const char* l = reinterpret_cast<const char*>(stage);
           unstage_region<PS>(l, slot, pv);
           fam.load(pv);
           unstage_region<N>(l + StageLayout<PS, N>::U0_OFFSET, slot, u);
         } else {
+          s = a.sys ? (int64_t)a.sys[t] : t;
+          uo = a.u_off ? a.u_off[s] : s * N;
           fam.load(a.params + (a.p_off ? a.p_off[s] : s * a.P));
 #pragma unroll
           for (int i = 0; i < N; ++i) u[i] = a.u0[uo + i];
+          // complete here, so that the paths join with no load in flight
+          __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
         }
       }
       buf_next += take;
       if (buf_next == buf_cnt) {
-        // chunk handed out: once every lane has read its slot, start copying
-        // the next chunk into the same buffer
-        __builtin_amdgcn_s_waitcnt(0);
+        // chunk handed out: once every lane's LDS reads have returned, start
+        // copying the next chunk into the same buffer
+        __builtin_amdgcn_s_waitcnt(WAITCNT_LGKM0);
         wave_sync();
-        chunk = next_chunk(chunk);
+        chunk = next_chunk();
         buf_next = 0;
         buf_cnt = chunk < nchunks ? (int)min<int64_t>(64, count - chunk * 64) : 0;
-        if (staged && chunk < nchunks) {
-          stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
-          buf_wait = true;
-        }
+        if (staged && chunk < nchunks) stage_chunk<PS, N>(a.params, a.u0, chunk * 64, stage_lds, buf_cnt);
       }
       if (fresh) {
         fam.residual(u, F, aux);
@@ -600,7 +614,10 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         else if (maxit == 0) finish(RC_MAXITERS, 0);
       }
     }
-    if (__all(st == ST_IDLE) && chunk >= nchunks) break;
+    // every lane idle and no chunk left: the rest of this trip does nothing,
+    // and the loop ends after it (an exit here would join the loop's back
+    // edge ahead of the trip's wait for the chunk copy)
+    const bool quit = __all(st == ST_IDLE) && chunk >= nchunks;
     // no system needs more trips than trip_cap: past it, end the system as
     // invalid rather than loop (iters = -1 - k, fnorm = trips)
     if (st != ST_IDLE && ++trips > trip_cap) {
@@ -707,6 +724,10 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
       }
     }
 
+    // the chunk copy issued in this trip's refill completes here (see above)
+    __builtin_amdgcn_s_waitcnt(WAITCNT_VM0);
+    wave_sync();
+
     // ---------------- trial point, residual, decision ----------------
     if (st == ST_TRIAL) {
       double ut[N], Ft[N], auxt[N];
@@ -807,6 +828,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         }
       }
     }
+    if (quit) break;
   }
 }
 
