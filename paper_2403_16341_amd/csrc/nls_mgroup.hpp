@@ -30,16 +30,25 @@ template <int NB, int L> struct MGeom {
   static_assert(R * L == NB && (L == 8 || L == 16 || L == 32), "bucket = rows per lane x group width");
 };
 
+// Strides: the groups of a wavefront read their own copies of these arrays at
+// the same offsets, so each group's row is padded to NB + 2 doubles (144 B for
+// NB = 16): the eight groups then fall on disjoint LDS banks.  The per-lane
+// column sums of a group are rows of NB + 2 doubles (eight lanes writing 16 B
+// each cover all banks) and each group's block is padded by 8 doubles more,
+// so that two groups reading them together also fall on distinct banks.
 template <int NB, int L, typename TI> struct MShared {
   static constexpr int G = 64 / L;
-  double x[G][NB];      // evaluation point (cubic) or its column map tanh(x) (tanh)
-  double dphi[G][NB];   // dual derivative of the column map at the iterate (tanh)
-  double cs[G][L][NB];  // per-lane column sums sum_r A_{r L + q, j} F_{r L + q}
+  static constexpr int RS = NB + 2;          // row stride of the per-group arrays
+  static constexpr int CS_ROW = NB + 2;      // per-lane row of the column sums
+  static constexpr int CS_GRP = L * CS_ROW + 8;
+  double x[G][RS];      // evaluation point (cubic) or its column map tanh(x) (tanh)
+  double dphi[G][RS];   // dual derivative of the column map at the iterate (tanh)
+  double cs[G][CS_GRP]; // per-lane column sums sum_r A_{r L + q, j} F_{r L + q}
   TI piv[G][NB + 2];    // pivot row of the current elimination step (columns k..) and its RHS
   int ppos[G];          // the pivot row's logical position
-  TI sol[G][NB];        // solution of the triangular solves
-  TI gv[G][NB];         // g = J^T F
-  TI jg[G][NB];         // J g
+  TI sol[G][RS];        // solution of the triangular solves
+  TI gv[G][RS];         // g = J^T F
+  TI jg[G][RS];         // J g
 };
 
 // group sum / max / any of per-row values (this lane's rows first, in row
@@ -108,15 +117,15 @@ template <int NB, int L> struct MRowsBase {
         c0 = __builtin_fma(A[r][j], F[r], c0);
         c1 = __builtin_fma(A[r][j + 1], F[r], c1);
       }
-      *reinterpret_cast<double2*>(&sh.cs[gi][q][j]) = double2{c0, c1};
+      *reinterpret_cast<double2*>(&sh.cs[gi][q * MShared<NB, L, TI>::CS_ROW + j]) = double2{c0, c1};
     }
     wave_sync();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = r * L + q;
-      double s = sh.cs[gi][0][j];
+      double s = sh.cs[gi][j];
 #pragma unroll
-      for (int l = 1; l < L; ++l) s = s + sh.cs[gi][l][j];
+      for (int l = 1; l < L; ++l) s = s + sh.cs[gi][l * MShared<NB, L, TI>::CS_ROW + j];
       out[r] = s;
     }
     wave_sync();
