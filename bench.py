@@ -474,7 +474,9 @@ def headline_leg(nls, args):
                        "mean_iters": float(it.mean()), "mean_trials": float((nf - 1).mean())},
         "fp32_inner": {"value": conv32 / step32, "ms_per_step": step32 * 1e3, "kernel_ms": float(np.mean(gpu32)),
                        "converged": conv32, "max_rel_diff_vs_fp64": float(rel.max()),
-                       "p50_rel_diff_vs_fp64": float(np.median(rel)), "roofline_split": split32},
+                       "p50_rel_diff_vs_fp64": float(np.median(rel)), "roofline_split": split32,
+                       "mean_iters": float(c32["iters"].cpu().numpy().mean()),
+                       "mean_trials": float((c32["nfev"].cpu().numpy() - 1).mean())},
         "retcodes_fp64": np.bincount(rc64, minlength=7).tolist(),
     }
 

@@ -39,6 +39,16 @@ __device__ __forceinline__ bool finite64(double x) { return __builtin_isfinite(x
 __device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
 template <typename T> __device__ __forceinline__ bool fin(T x) { return __builtin_isfinite(x); }
 
+// Multiply-add, square root and magnitude in the operands' own precision: the
+// unsuffixed builtins take double, so a float operand would be widened,
+// computed in FP64 and rounded twice.
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float sqrtt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrtt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float fabst(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double fabst(double x) { return __builtin_fabs(x); }
+
 // s_waitcnt operands (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
 // 6:4, lgkmcnt in 11:8; a field at its maximum does not wait)
 enum : int { WAITCNT_VM0 = 0x0F70, WAITCNT_LGKM0 = 0xC07F };
@@ -112,7 +122,7 @@ template <int N> struct LaneFam<N, FAM_CUBIC> {
     for (int i = 0; i < N; ++i) {
       double s = A[i][0] * u[0];
 #pragma unroll
-      for (int j = 1; j < N; ++j) s = __builtin_fma(A[i][j], u[j], s);
+      for (int j = 1; j < N; ++j) s = fmat(A[i][j], u[j], s);
       double cube = u[i] * u[i] * u[i];
       F[i] = (s + 0.1 * cube) - b[i];
       aux[i] = 0.0;
@@ -150,7 +160,7 @@ template <int N> struct LaneFam<N, FAM_TANH> {
     for (int i = 0; i < N; ++i) {
       double s = A[i][0] * aux[0];
 #pragma unroll
-      for (int j = 1; j < N; ++j) s = __builtin_fma(A[i][j], aux[j], s);
+      for (int j = 1; j < N; ++j) s = fmat(A[i][j], aux[j], s);
       F[i] = (s + beta * u[i]) - b[i];
     }
   }
@@ -237,10 +247,10 @@ template <int N> struct LaneFam<N, FAM_PAPER> {
 // Zero and non-finite pivots never reach it (they end the factorisation).
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
+  double e = fmat(-x, r, 1.0);
+  r = fmat(r, e, r);
+  e = fmat(-x, r, 1.0);
+  return fmat(r, e, r);
 }
 __device__ __forceinline__ float recip(float x) {
   float r = __builtin_amdgcn_rcpf(x);
@@ -267,17 +277,17 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N], int* pr =
     // keeps the pivot unless some later |a_ik| is strictly larger than |a_kk|
     // (one compare per candidate); the full running-maximum search runs only
     // when that happens on some lane of the wavefront.
-    const T dkk = __builtin_fabs(a[k][k]);
+    const T dkk = fabst(a[k][k]);
     bool larger = false;
 #pragma unroll
-    for (int i = k + 1; i < N; ++i) larger = larger || (__builtin_fabs(a[i][k]) > dkk);
+    for (int i = k + 1; i < N; ++i) larger = larger || (fabst(a[i][k]) > dkk);
     int p = k;
     if (__any(larger)) {
       __asm__ volatile("" ::: "memory");
       T best = dkk;
 #pragma unroll
       for (int i = k + 1; i < N; ++i) {
-        T v = __builtin_fabs(a[i][k]);
+        T v = fabst(a[i][k]);
         bool c = v > best;
         best = c ? v : best;
         p = c ? i : p;
@@ -312,15 +322,15 @@ __device__ __forceinline__ bool lane_lu_solve(T (&a)[N][N], T (&x)[N], int* pr =
       const T l = a[i][k] * r;
       if constexpr (KEEP) a[i][k] = l;
 #pragma unroll
-      for (int j = k + 1; j < N; ++j) a[i][j] = __builtin_fma(-l, a[k][j], a[i][j]);
-      x[i] = __builtin_fma(-l, x[k], x[i]);
+      for (int j = k + 1; j < N; ++j) a[i][j] = fmat(-l, a[k][j], a[i][j]);
+      x[i] = fmat(-l, x[k], x[i]);
     }
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     T s = x[i];
 #pragma unroll
-    for (int j = i + 1; j < N; ++j) s = __builtin_fma(-a[i][j], x[j], s);
+    for (int j = i + 1; j < N; ++j) s = fmat(-a[i][j], x[j], s);
     x[i] = s * a[i][i];
   }
   return ok;
@@ -344,13 +354,13 @@ __device__ __forceinline__ void lane_lu_resolve(const T (&a)[N][N], const int (&
       }
     }
 #pragma unroll
-    for (int i = k + 1; i < N; ++i) x[i] = __builtin_fma(-a[i][k], x[k], x[i]);
+    for (int i = k + 1; i < N; ++i) x[i] = fmat(-a[i][k], x[k], x[i]);
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     T s = x[i];
 #pragma unroll
-    for (int j = i + 1; j < N; ++j) s = __builtin_fma(-a[i][j], x[j], s);
+    for (int j = i + 1; j < N; ++j) s = fmat(-a[i][j], x[j], s);
     x[i] = s * a[i][i];
   }
 }
@@ -364,13 +374,13 @@ template <int N> __device__ __forceinline__ bool all_finite(const double (&F)[N]
 template <int N> __device__ __forceinline__ double norm_inf(const double (&F)[N]) {
   double m = 0.0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) m = fmax(m, __builtin_fabs(F[i]));
+  for (int i = 0; i < N; ++i) m = fmax(m, fabst(F[i]));
   return m;
 }
 template <int N, typename T> __device__ __forceinline__ T sumsq(const T (&x)[N]) {
   T s = x[0] * x[0];
 #pragma unroll
-  for (int i = 1; i < N; ++i) s = __builtin_fma(x[i], x[i], s);
+  for (int i = 1; i < N; ++i) s = fmat(x[i], x[i], s);
   return s;
 }
 
@@ -688,14 +698,14 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           for (int j = 0; j < N; ++j) {
             TI sacc = J[0][j] * Ff[0];
 #pragma unroll
-            for (int i = 1; i < N; ++i) sacc = __builtin_fma(J[i][j], Ff[i], sacc);
+            for (int i = 1; i < N; ++i) sacc = fmat(J[i][j], Ff[i], sacc);
             g[j] = sacc;
           }
 #pragma unroll
           for (int i = 0; i < N; ++i) {
             TI sacc = J[i][0] * g[0];
 #pragma unroll
-            for (int j = 1; j < N; ++j) sacc = __builtin_fma(J[i][j], g[j], sacc);
+            for (int j = 1; j < N; ++j) sacc = fmat(J[i][j], g[j], sacc);
             Jg[i] = sacc;
           }
 #pragma unroll
@@ -703,7 +713,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           if (!lane_lu_solve<N, TI>(J, dN)) {
             finish(RC_SINGULAR, k);
           } else {
-            nN = __builtin_sqrt(sumsq<N, TI>(dN));
+            nN = sqrtt(sumsq<N, TI>(dN));
             ng2 = sumsq<N, TI>(g);
             nJg2 = sumsq<N, TI>(Jg);
             // the Cauchy point and the dogleg segment do not depend on the radius
@@ -716,7 +726,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
             qa = sumsq<N, TI>(dd);
             TI dcd = dC[0] * dd[0];
 #pragma unroll
-            for (int i = 1; i < N; ++i) dcd = __builtin_fma(dC[i], dd[i], dcd);
+            for (int i = 1; i < N; ++i) dcd = fmat(dC[i], dd[i], dcd);
             qb = TI(2) * dcd;
             st = ST_TRIAL;
           }
@@ -738,7 +748,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         for (int i = 0; i < N; ++i) ut[i] = u[i] + d[i];
       } else if (ALG == ALG_ARMIJO) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) ut[i] = __builtin_fma(alpha, d[i], u[i]);
+        for (int i = 0; i < N; ++i) ut[i] = fmat(alpha, d[i], u[i]);
       } else {
         // dogleg step for the current radius (step algebra in TI)
         const TI D = (TI)Delta;
@@ -752,8 +762,8 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           for (int i = 0; i < N; ++i) step[i] = (double)(dN[i] * r);
           const double om = 1.0 - (double)r;
           pred = phi * (1.0 - om * om);  // F + J step = (1 - r) F
-        } else if (__builtin_sqrt(nC2) >= D) {
-          const TI sc = D / __builtin_sqrt(ng2);
+        } else if (sqrtt(nC2) >= D) {
+          const TI sc = D / sqrtt(ng2);
 #pragma unroll
           for (int i = 0; i < N; ++i) step[i] = (double)(-sc * g[i]);
           // ||F - sc Jg||^2 = phi - 2 sc ||g||^2 + sc^2 ||Jg||^2, as F.Jg = ||g||^2
@@ -761,10 +771,10 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
         } else {
           const TI qc = nC2 - D * D;
           const TI disc = qb * qb - TI(4) * qa * qc;
-          const TI sq = __builtin_sqrt(disc);
+          const TI sq = sqrtt(disc);
           const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
 #pragma unroll
-          for (int i = 0; i < N; ++i) step[i] = (double)__builtin_fma(tau, dd[i], dC[i]);
+          for (int i = 0; i < N; ++i) step[i] = (double)fmat(tau, dd[i], dC[i]);
           // F + J step = (1 - tau)(F - tC Jg), ||F - tC Jg||^2 = phi - tC ||g||^2
           const double om = 1.0 - (double)tau;
           pred = phi - om * om * (phi - (double)tC * (double)ng2);
@@ -811,7 +821,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           accept = true;
         } else {
           accept = false;
-          Delta = o.shrink * __builtin_sqrt(sumsq<N, double>(step));
+          Delta = o.shrink * sqrtt(sumsq<N, double>(step));
         }
         if (accept) {
 #pragma unroll
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(64) void k_lane(const KArgs a) {
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
           else st = ST_DIR;
         } else {
-          const double un = __builtin_sqrt(sumsq<N, double>(u));
+          const double un = sqrtt(sumsq<N, double>(u));
           if (Delta < o.collapse * fmax(1.0, un)) finish(RC_TR_COLLAPSED, k);
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
         }
@@ -953,12 +963,12 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ arow, const
   const double2* v2 = reinterpret_cast<const double2*>(v);
   double2 a0 = a2[0], v0 = v2[0];
   double s = a0.x * v0.x;
-  s = __builtin_fma(a0.y, v0.y, s);
+  s = fmat(a0.y, v0.y, s);
 #pragma unroll
   for (int h = 1; h < NB / 2; ++h) {
     const double2 ah = a2[h], vh = v2[h];
-    s = __builtin_fma(ah.x, vh.x, s);
-    s = __builtin_fma(ah.y, vh.y, s);
+    s = fmat(ah.x, vh.x, s);
+    s = fmat(ah.y, vh.y, s);
   }
   return s;
 }
@@ -968,7 +978,7 @@ template <int NB>
 __device__ __forceinline__ double col_dot(const double (&a)[NB][NB + 2], int r, const double* __restrict__ w) {
   double s = a[0][r] * w[0];
 #pragma unroll
-  for (int i = 1; i < NB; ++i) s = __builtin_fma(a[i][r], w[i], s);
+  for (int i = 1; i < NB; ++i) s = fmat(a[i][r], w[i], s);
   return s;
 }
 
@@ -1013,7 +1023,7 @@ template <int NB> struct RowFam<NB, FAM_CUBIC> {
     wave_sync();
     const double s = own ? col_dot<NB>(A.a[gi], r, sh.fv[gi]) : 0.0;
     wave_sync();
-    return own ? __builtin_fma(cubic_term_deriv(ur), Fr, s) : 0.0;
+    return own ? fmat(cubic_term_deriv(ur), Fr, s) : 0.0;
   }
 };
 
@@ -1063,7 +1073,7 @@ template <int NB> struct RowFam<NB, FAM_TANH> {
     wave_sync();
     const double s = own ? col_dot<NB>(A.a[gi], r, sh.fv[gi]) : 0.0;
     wave_sync();
-    return own ? __builtin_fma(beta, Fr, dtanh_known(dseed(ur), auxr).d * s) : 0.0;
+    return own ? fmat(beta, Fr, dtanh_known(dseed(ur), auxr).d * s) : 0.0;
   }
 };
 
@@ -1150,7 +1160,7 @@ __device__ __forceinline__ void group_back_substitute(GroupShared<NB, L, TI>& sh
       if (k < n) {
         const TI xk = wave_bcast(rhs * myrd, wave_lane_of(pos == k));
         if (r == k) mine = xk;
-        if (own && pos < k) rhs = __builtin_fma(-J[k], xk, rhs);
+        if (own && pos < k) rhs = fmat(-J[k], xk, rhs);
       }
     }
     if (own) sh.sol[gi][r] = mine;
@@ -1161,7 +1171,7 @@ __device__ __forceinline__ void group_back_substitute(GroupShared<NB, L, TI>& sh
       if (k < n) {
         if (pos == k) sh.sol[gi][k] = rhs * myrd;
         wave_sync();
-        if (own && pos < k) rhs = __builtin_fma(-J[k], sh.sol[gi][k], rhs);
+        if (own && pos < k) rhs = fmat(-J[k], sh.sol[gi][k], rhs);
         wave_sync();
       }
     }
@@ -1193,7 +1203,7 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
       // the row in position k wins every tie and keeps a NaN (-> singular);
       // other NaN rows never win: they rank below every number
       const bool nan_at_k = grp_any<L>(pos == k && v != v);
-      const TI key = cand ? (v != v ? TI(-1) : __builtin_fabs(v)) : TI(-2);
+      const TI key = cand ? (v != v ? TI(-1) : fabst(v)) : TI(-2);
       // the group's largest key, then the row holding it: usually one lane
       // does; on a tie the smallest position among them wins
       const TI mx = grp_max<L>(key);
@@ -1223,9 +1233,9 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
 #pragma unroll
         for (int j = k + 1; j < NB; ++j) {
           const TI pj = wave_bcast(J[j], pl);  // read before this step changes any row
-          if (upd) J[j] = __builtin_fma(-l, pj, J[j]);
+          if (upd) J[j] = fmat(-l, pj, J[j]);
         }
-        if (upd) rhs = __builtin_fma(-l, prhs, rhs);
+        if (upd) rhs = fmat(-l, prhs, rhs);
       } else {
         // the pivot row publishes columns k.., its RHS and its position
         if (owner) {
@@ -1247,8 +1257,8 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
           const TI l = J[k] * rp;
           J[k] = l;
 #pragma unroll
-          for (int j = k + 1; j < NB; ++j) J[j] = __builtin_fma(-l, sh.piv[gi][j], J[j]);
-          rhs = __builtin_fma(-l, sh.piv[gi][NB], rhs);
+          for (int j = k + 1; j < NB; ++j) J[j] = fmat(-l, sh.piv[gi][j], J[j]);
+          rhs = fmat(-l, sh.piv[gi][NB], rhs);
         }
         wave_sync();
       }
@@ -1278,11 +1288,11 @@ __device__ __forceinline__ void group_lu_resolve(GroupShared<NB, L, TI>& sh, int
     if (k < n) {
       if constexpr (L == 64) {
         const TI rk = wave_bcast(rhs, wave_lane_of(pos == k));
-        if (own && pos > k) rhs = __builtin_fma(-J[k], rk, rhs);
+        if (own && pos > k) rhs = fmat(-J[k], rk, rhs);
       } else {
         if (pos == k) sh.piv[gi][NB] = rhs;
         wave_sync();
-        if (own && pos > k) rhs = __builtin_fma(-J[k], sh.piv[gi][NB], rhs);
+        if (own && pos > k) rhs = fmat(-J[k], sh.piv[gi][NB], rhs);
         wave_sync();
       }
     }
@@ -1358,7 +1368,7 @@ void k_group(const KArgs a) {
   };
   auto set_norms = [&]() {
     const bool fin_ = !grp_any<L>(!finite64(F));
-    fcur = fin_ ? grp_max<L>(__builtin_fabs(F)) : __builtin_inf();
+    fcur = fin_ ? grp_max<L>(fabst(F)) : __builtin_inf();
     phi = grp_sum<L>(F * F);
     return fin_;
   };
@@ -1478,7 +1488,7 @@ void k_group(const KArgs a) {
         wave_sync();
         TI jg = J[0] * sh.gv[gi][0];
 #pragma unroll
-        for (int j = 1; j < NB; ++j) jg = __builtin_fma(J[j], sh.gv[gi][j], jg);
+        for (int j = 1; j < NB; ++j) jg = fmat(J[j], sh.gv[gi][j], jg);
         const TI Jg = own ? jg : TI(0);
         wave_sync();
         if (!group_lu_solve<NB, L, TI>(sh, gi, r, n, J, -Ff)) {
@@ -1486,7 +1496,7 @@ void k_group(const KArgs a) {
         } else {
           dN = own ? sh.sol[gi][r] : TI(0);
           wave_sync();
-          nN = __builtin_sqrt(grp_sum<L>(dN * dN));
+          nN = sqrtt(grp_sum<L>(dN * dN));
           ng2 = grp_sum<L>(g * g);
           nJg2 = grp_sum<L>(Jg * Jg);
           tC = ng2 / nJg2;
@@ -1506,7 +1516,7 @@ void k_group(const KArgs a) {
       if (ALG == ALG_NEWTON || ALG == ALG_POTRA) {
         ut = u + d;
       } else if (ALG == ALG_ARMIJO) {
-        ut = __builtin_fma(alpha, d, u);
+        ut = fmat(alpha, d, u);
       } else {
         const TI D = (TI)Delta;
         if ((double)nN <= Delta) {
@@ -1517,16 +1527,16 @@ void k_group(const KArgs a) {
           step = (double)(dN * rr);
           const double om = 1.0 - (double)rr;
           pred = phi * (1.0 - om * om);
-        } else if (__builtin_sqrt(nC2) >= D) {
-          const TI sc = D / __builtin_sqrt(ng2);
+        } else if (sqrtt(nC2) >= D) {
+          const TI sc = D / sqrtt(ng2);
           step = (double)(-sc * g);
           pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
         } else {
           const TI qc = nC2 - D * D;
           const TI disc = qb * qb - TI(4) * qa * qc;
-          const TI sq = __builtin_sqrt(disc);
+          const TI sq = sqrtt(disc);
           const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
-          step = (double)__builtin_fma(tau, dd, dC);
+          step = (double)fmat(tau, dd, dC);
           const double om = 1.0 - (double)tau;
           pred = phi - om * om * (phi - (double)tC * (double)ng2);
         }
@@ -1572,7 +1582,7 @@ void k_group(const KArgs a) {
           accept = true;
         } else {
           accept = false;
-          Delta = o.shrink * __builtin_sqrt(grp_sum<L>(step * step));
+          Delta = o.shrink * sqrtt(grp_sum<L>(step * step));
         }
         if (accept) {
           u = ut;
@@ -1583,7 +1593,7 @@ void k_group(const KArgs a) {
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
           else gst = ST_DIR;
         } else {
-          const double un = __builtin_sqrt(grp_sum<L>(u * u));
+          const double un = sqrtt(grp_sum<L>(u * u));
           if (Delta < o.collapse * fmax(1.0, un)) finish(RC_TR_COLLAPSED, k);
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
         }

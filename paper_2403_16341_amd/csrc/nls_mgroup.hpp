@@ -95,12 +95,12 @@ template <int NB, int L> struct MRowsBase {
     const double2* v2 = reinterpret_cast<const double2*>(v);
     double2 v0 = v2[0];
     double s = A[r][0] * v0.x;
-    s = __builtin_fma(A[r][1], v0.y, s);
+    s = fmat(A[r][1], v0.y, s);
 #pragma unroll
     for (int h = 1; h < NB / 2; ++h) {
       const double2 vh = v2[h];
-      s = __builtin_fma(A[r][2 * h], vh.x, s);
-      s = __builtin_fma(A[r][2 * h + 1], vh.y, s);
+      s = fmat(A[r][2 * h], vh.x, s);
+      s = fmat(A[r][2 * h + 1], vh.y, s);
     }
     return s;
   }
@@ -114,8 +114,8 @@ template <int NB, int L> struct MRowsBase {
       double c0 = A[0][j] * F[0], c1 = A[0][j + 1] * F[0];
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        c0 = __builtin_fma(A[r][j], F[r], c0);
-        c1 = __builtin_fma(A[r][j + 1], F[r], c1);
+        c0 = fmat(A[r][j], F[r], c0);
+        c1 = fmat(A[r][j + 1], F[r], c1);
       }
       *reinterpret_cast<double2*>(&sh.cs[gi][q * MShared<NB, L, TI>::CS_ROW + j]) = double2{c0, c1};
     }
@@ -170,7 +170,7 @@ template <int NB, int L> struct MRows<NB, L, FAM_CUBIC> : MRowsBase<NB, L> {
     double cs[R];
     Base::col_sums(sh, gi, q, F, cs);
 #pragma unroll
-    for (int r = 0; r < R; ++r) g[r] = (r * L + q < n) ? __builtin_fma(cubic_term_deriv(u[r]), F[r], cs[r]) : 0.0;
+    for (int r = 0; r < R; ++r) g[r] = (r * L + q < n) ? fmat(cubic_term_deriv(u[r]), F[r], cs[r]) : 0.0;
   }
 };
 
@@ -230,7 +230,7 @@ template <int NB, int L> struct MRows<NB, L, FAM_TANH> : MRowsBase<NB, L> {
     Base::col_sums(sh, gi, q, F, cs);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      g[r] = (r * L + q < n) ? __builtin_fma(beta, F[r], dtanh_known(dseed(u[r]), aux[r]).d * cs[r]) : 0.0;
+      g[r] = (r * L + q < n) ? fmat(beta, F[r], dtanh_known(dseed(u[r]), aux[r]).d * cs[r]) : 0.0;
   }
 };
 
@@ -276,7 +276,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         nan_k = nan_k || (pos[r] == k && v != v);
         const bool cand = pos[r] >= k && pos[r] < NB;
         // NaN rows rank below every number, non-candidates below those
-        const TI kr = cand ? (v != v ? TI(-1) : __builtin_fabs(v)) : TI(-2);
+        const TI kr = cand ? (v != v ? TI(-1) : fabst(v)) : TI(-2);
         const bool take = kr > key || (kr == key && pos[r] < kp);
         key = take ? kr : key;
         kp = take ? pos[r] : kp;
@@ -333,8 +333,8 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
           const TI l = J[r][k] * rp;
           J[r][k] = l;
 #pragma unroll
-          for (int j = k + 1; j < NB; ++j) J[r][j] = __builtin_fma(-l, sh.piv[gi][j], J[r][j]);
-          x[r] = __builtin_fma(-l, sh.piv[gi][NB], x[r]);
+          for (int j = k + 1; j < NB; ++j) J[r][j] = fmat(-l, sh.piv[gi][j], J[r][j]);
+          x[r] = fmat(-l, sh.piv[gi][NB], x[r]);
         }
       }
       wave_sync();
@@ -351,7 +351,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
       const TI xk = sh.sol[gi][k];
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (own[r] && pos[r] < k) x[r] = __builtin_fma(-J[r][k], xk, x[r]);
+        if (own[r] && pos[r] < k) x[r] = fmat(-J[r][k], xk, x[r]);
       wave_sync();
     }
   });
@@ -430,7 +430,7 @@ void k_mgroup(const KArgs a) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       bad[r] = !finite64(Fv[r]);
-      av[r] = __builtin_fabs(Fv[r]);
+      av[r] = fabst(Fv[r]);
       sq[r] = Fv[r] * Fv[r];
     }
     const bool fin_ = !mg_any<L, R>(bad);
@@ -532,7 +532,7 @@ void k_mgroup(const KArgs a) {
         for (int r = 0; r < R; ++r) {
           TI acc = J[r][0] * sh.gv[gi][0];
 #pragma unroll
-          for (int j = 1; j < NB; ++j) acc = __builtin_fma(J[r][j], sh.gv[gi][j], acc);
+          for (int j = 1; j < NB; ++j) acc = fmat(J[r][j], sh.gv[gi][j], acc);
           sh.jg[gi][r * L + q] = own(r) ? acc : TI(0);
         }
         wave_sync();
@@ -553,7 +553,7 @@ void k_mgroup(const KArgs a) {
             sJg[r] = jg * jg;
           }
           wave_sync();
-          nN = __builtin_sqrt(mg_sum<L, R>(sN));
+          nN = sqrtt(mg_sum<L, R>(sN));
           ng2 = mg_sum<L, R>(sg);
           nJg2 = mg_sum<L, R>(sJg);
           tC = ng2 / nJg2;
@@ -583,7 +583,7 @@ void k_mgroup(const KArgs a) {
         for (int r = 0; r < R; ++r) ut[r] = u[r] + d[r];
       } else if (ALG == ALG_ARMIJO) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) ut[r] = __builtin_fma(alpha, d[r], u[r]);
+        for (int r = 0; r < R; ++r) ut[r] = fmat(alpha, d[r], u[r]);
       } else {
         const TI D = (TI)Delta;
         if ((double)nN <= Delta) {
@@ -596,20 +596,20 @@ void k_mgroup(const KArgs a) {
           for (int r = 0; r < R; ++r) step[r] = (double)(dN[r] * rr);
           const double om = 1.0 - (double)rr;
           pred = phi * (1.0 - om * om);
-        } else if (__builtin_sqrt(nC2) >= D) {
-          const TI sc = D / __builtin_sqrt(ng2);
+        } else if (sqrtt(nC2) >= D) {
+          const TI sc = D / sqrtt(ng2);
 #pragma unroll
           for (int r = 0; r < R; ++r) step[r] = (double)(-sc * g[r]);
           pred = (double)sc * (2.0 * (double)ng2 - (double)sc * (double)nJg2);
         } else {
           const TI qc = nC2 - D * D;
           const TI disc = qb * qb - TI(4) * qa * qc;
-          const TI sq = __builtin_sqrt(disc);
+          const TI sq = sqrtt(disc);
           const TI tau = (qb <= TI(0)) ? (-qb + sq) / (TI(2) * qa) : (TI(-2) * qc) / (qb + sq);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const TI dc = -tC * g[r];
-            step[r] = (double)__builtin_fma(tau, dN[r] - dc, dc);
+            step[r] = (double)fmat(tau, dN[r] - dc, dc);
           }
           const double om = 1.0 - (double)tau;
           pred = phi - om * om * (phi - (double)tC * (double)ng2);
@@ -670,7 +670,7 @@ void k_mgroup(const KArgs a) {
           double s2[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) s2[r] = step[r] * step[r];
-          Delta = o.shrink * __builtin_sqrt(mg_sum<L, R>(s2));
+          Delta = o.shrink * sqrtt(mg_sum<L, R>(s2));
         }
         if (accept) {
 #pragma unroll
@@ -688,7 +688,7 @@ void k_mgroup(const KArgs a) {
           double u2[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) u2[r] = u[r] * u[r];
-          const double un = __builtin_sqrt(mg_sum<L, R>(u2));
+          const double un = sqrtt(mg_sum<L, R>(u2));
           if (Delta < o.collapse * fmax(1.0, un)) finish(RC_TR_COLLAPSED, k);
           else if (k >= maxit) finish(RC_MAXITERS, maxit);
         }

@@ -110,10 +110,10 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
         const double* __restrict__ v = a.seed + po;
         double sdot = 0.0;
         if constexpr (FAM == FAM_CUBIC) {
-          for (int j = 0; j < n; ++j) sdot = __builtin_fma(v[r * n + j], xs[gi][j], sdot);
+          for (int j = 0; j < n; ++j) sdot = fmat(v[r * n + j], xs[gi][j], sdot);
           sdot = sdot - v[n * n + r];
         } else if constexpr (FAM == FAM_TANH) {
-          for (int j = 0; j < n; ++j) sdot = __builtin_fma(v[r * n + j], ts[gi][j], sdot);
+          for (int j = 0; j < n; ++j) sdot = fmat(v[r * n + j], ts[gi][j], sdot);
           sdot = (sdot - v[n * n + r]) + v[n * n + n] * u;
         } else if constexpr (FAM == FAM_PAPER) {
           if (r == 0) {
