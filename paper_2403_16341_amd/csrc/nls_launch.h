@@ -74,6 +74,14 @@ struct SensArgs {
   int32_t n;
 };
 // size bucket of the sensitivity kernels: 8, 16, 24, ..., 64
+// Persistent grid under a cap of pct percent of the resident wavefronts
+// (pct <= 0 or >= 100: no cap; at least one wavefront).
+inline int grid_cap(int waves, int pct) {
+  if (pct <= 0 || pct >= 100) return waves;
+  const int c = (int)((int64_t)waves * pct / 100);
+  return c > 0 ? c : 1;
+}
+
 inline int sens_bucket(int n) { return n <= 8 ? 8 : (n + 7) / 8 * 8; }
 int launch_sens(int nb, int fam, int mode, const SensArgs& a, hipStream_t st);
 

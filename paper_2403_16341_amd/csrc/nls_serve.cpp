@@ -176,6 +176,7 @@ int32_t enqueue(nls_server* s, InFlight& L) {
     a.maxiters = q0.b.maxiters;
     a.abstol = q0.b.abstol;
     a.o = to_kopts(q0.opts);
+    if (s->streams.size() > 1 && launch_work(L.plan.m, q0.n) > kExpressWork) a.grid_pct = kLargeGridPct;
     if (launch(mp.key_n, mp.lane, q0.fam, chain ? ALG_NEWTON : q0.alg, q0.b.precision, a, st) != 0)
       return NLS_E_DEVICE;
     if (chain) {

@@ -236,6 +236,12 @@ inline double launch_work(int64_t m, int n) { return (double)m * n * n * n; }
 // 256 at n = 64) may use stream 0; larger ones never do.
 constexpr double kExpressWork = 67108864.0;  // 2^26
 
+// Larger launches run on at most this share of the device's resident
+// wavefronts (percent): a persistent grid sized for the whole device would
+// hold every compute unit until its last system ends, so an express launch
+// queued meanwhile on stream 0 could not start.
+constexpr int kLargeGridPct = 75;
+
 // Stream for a launch: the least-loaded one (ties: lowest index).  With more
 // than one stream, stream 0 is kept for small launches, so a small request
 // never waits behind a large one in stream order.

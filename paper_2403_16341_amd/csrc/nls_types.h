@@ -67,7 +67,7 @@ struct KArgs {
   double abstol;
   KOpts o;
   int32_t rows;         // group kernels of the n <= 16 bucket: rows per lane (1 or 2; 0 = the default)
-  int32_t pad2;
+  int32_t grid_pct;     // persistent grid cap, percent of the resident wavefronts (0 = no cap)
 };
 
 }  // namespace nls
