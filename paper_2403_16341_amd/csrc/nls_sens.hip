@@ -59,6 +59,26 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
     wave_sync();
     bool bad = own && !finite64(u);
 
+    // ---- this lane's parameters, loaded up front: one wait for all of them
+    // instead of one round trip per column (indices past n are clamped to a
+    // valid entry and the values dropped) ----
+    double pa[NB];
+    double beta = 0.0, br = 0.0, wr = 0.0;
+    if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) pa[c] = 0.0;
+      if (own) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const int cc = c < n ? c : n - 1;
+          pa[c] = MODE == SENS_TANGENT ? p[r * n + cc] : p[cc * n + r];
+        }
+        br = p[n * n + r];
+        if constexpr (FAM == FAM_TANH) beta = p[n * n + n];
+        if constexpr (MODE == SENS_ADJOINT) wr = a.seed[uo + r];
+      }
+    }
+
     // ---- this lane's row of J (tangent) or of J^T (adjoint), in registers ----
     // entry (i, j) of J is dF_i/du_j, the forward-mode tangent of F_i for the
     // seed u_j + eps; the adjoint form takes column r of J as its row r
@@ -70,14 +90,14 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
         const int i = MODE == SENS_TANGENT ? r : c;  // row of J
         const int j = MODE == SENS_TANGENT ? c : r;  // column of J
         if constexpr (FAM == FAM_CUBIC) {
-          const double aij = p[i * n + j];
+          const double aij = pa[c];
           bad |= !finite64(aij);
           v = i == j ? aij + cubic_term_deriv(xs[gi][i]) : aij;
         } else if constexpr (FAM == FAM_TANH) {
-          const double aij = p[i * n + j];
+          const double aij = pa[c];
           bad |= !finite64(aij);
           const double w = aij * dtanh_known(dseed(xs[gi][j]), ts[gi][j]).d;
-          v = i == j ? w + p[n * n + n] : w;
+          v = i == j ? w + beta : w;
         } else if constexpr (FAM == FAM_ROSENBROCK) {
           if (i == 0) {
             v = j == 0 ? -1.0 : 0.0;
@@ -104,17 +124,30 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
     double rhs = 0.0;
     if (own) {
       if constexpr (MODE == SENS_ADJOINT) {
-        rhs = a.seed[uo + r];
+        if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) rhs = wr;
+        else rhs = a.seed[uo + r];
       } else {
         // -(dF_r/dtheta) . v, the parameter derivatives of row r
         const double* __restrict__ v = a.seed + po;
         double sdot = 0.0;
-        if constexpr (FAM == FAM_CUBIC) {
-          for (int j = 0; j < n; ++j) sdot = fmat(v[r * n + j], xs[gi][j], sdot);
-          sdot = sdot - v[n * n + r];
-        } else if constexpr (FAM == FAM_TANH) {
-          for (int j = 0; j < n; ++j) sdot = fmat(v[r * n + j], ts[gi][j], sdot);
-          sdot = (sdot - v[n * n + r]) + v[n * n + n] * u;
+        if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) {
+          // the direction's row r, loaded up front as the parameters above
+          double vr[NB];
+#pragma unroll
+          for (int j = 0; j < NB; ++j) vr[j] = v[r * n + (j < n ? j : n - 1)];
+          const double vb = v[n * n + r];
+          if constexpr (FAM == FAM_CUBIC) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+              if (j < n) sdot = fmat(vr[j], xs[gi][j], sdot);
+            sdot = sdot - vb;
+          } else {
+            const double vbeta = v[n * n + n];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+              if (j < n) sdot = fmat(vr[j], ts[gi][j], sdot);
+            sdot = (sdot - vb) + vbeta * u;
+          }
         } else if constexpr (FAM == FAM_PAPER) {
           if (r == 0) {
             const double u1 = xs[gi][1];
@@ -123,8 +156,8 @@ __global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
         }
         rhs = -sdot;
       }
-      if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) bad |= !finite64(p[n * n + r]);
-      if constexpr (FAM == FAM_TANH) bad |= !finite64(p[n * n + n]);
+      if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) bad |= !finite64(br);
+      if constexpr (FAM == FAM_TANH) bad |= !finite64(beta);
       if constexpr (FAM == FAM_PAPER) bad |= r == 0 && !(finite64(p[0]) && finite64(p[1]) && finite64(p[2]));
     }
     bad = grp_any<L>(bad);
