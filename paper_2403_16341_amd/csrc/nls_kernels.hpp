@@ -939,11 +939,40 @@ template <int NB, int FAM> struct RowFam;
 // consecutive lanes read consecutive doubles of a row.
 template <int NB, int L>
 __device__ __forceinline__ void stage_matrix(double (&a)[NB][NB + 2], const double* __restrict__ p, int n, int r) {
+  constexpr int E = (NB * NB) / L;
+  if constexpr (NB < 40) {
 #pragma unroll
-  for (int e = 0; e < (NB * NB) / L; ++e) {
-    const int idx = e * L + r;
-    const int i = idx / NB, j = idx % NB;
-    a[i][j] = (i < n && j < n) ? p[i * n + j] : 0.0;
+    for (int e = 0; e < E; ++e) {
+      const int idx = e * L + r;
+      const int i = idx / NB, j = idx % NB;
+      a[i][j] = (i < n && j < n) ? p[i * n + j] : 0.0;
+    }
+  } else {
+    // Large buckets: loads in batches of eight, issued back to back before
+    // any is used (a load per element behind its own branch waits for each in
+    // turn); entries outside n x n read p[0] and are stored as zero.  (Measured
+    // on the mixed batch, the smaller buckets run no faster this way.)
+    constexpr int B = 8;
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += B) {
+      double v[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (e0 + b < E) {
+          const int idx = (e0 + b) * L + r;
+          const int i = idx / NB, j = idx % NB;
+          v[b] = p[(i < n && j < n) ? i * n + j : 0];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (e0 + b < E) {
+          const int idx = (e0 + b) * L + r;
+          const int i = idx / NB, j = idx % NB;
+          a[i][j] = (i < n && j < n) ? v[b] : 0.0;
+        }
+      }
+    }
   }
 }
 

@@ -22,10 +22,13 @@ namespace {
 
 template <int NB> struct SensWidth {
   static constexpr int L = NB <= 16 ? 16 : (NB <= 32 ? 32 : 64);
+  // wavefronts per SIMD the kernel is compiled for: four up to NB = 24 (no
+  // spill at 128 registers), else the compiler's choice
+  static constexpr int W = NB <= 24 ? 4 : 1;
 };
 
 template <int NB, int L, int FAM, int MODE>
-__global__ __launch_bounds__(64) void k_sens(const SensArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SensWidth<NB>::W))) void k_sens(const SensArgs a) {
   constexpr int G = 64 / L;
   __shared__ __attribute__((aligned(16))) GroupShared<NB, L, double> sh;
   __shared__ double xs[G][NB];  // u
