@@ -53,18 +53,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SensWidth<NB
     const int64_t po = a.p_off ? a.p_off[s] : s * P;
     const double* __restrict__ p = a.params + po;
 
-    const double u = own ? a.u[uo + r] : 0.0;
-    const double tu = (FAM == FAM_TANH && own) ? tanh(u) : 0.0;
-    if (row) {
-      xs[gi][r] = u;
-      ts[gi][r] = tu;
-    }
-    wave_sync();
-    bool bad = own && !finite64(u);
-
-    // ---- this lane's parameters, loaded up front: one wait for all of them
-    // instead of one round trip per column (indices past n are clamped to a
-    // valid entry and the values dropped) ----
+    // ---- this lane's parameters, loaded up front together with u: one wait
+    // for all of them instead of one round trip per column (indices past n
+    // are clamped to a valid entry and the values dropped) ----
     double pa[NB];
     double beta = 0.0, br = 0.0, wr = 0.0;
     if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) {
@@ -81,6 +72,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SensWidth<NB
         if constexpr (MODE == SENS_ADJOINT) wr = a.seed[uo + r];
       }
     }
+
+    const double u = own ? a.u[uo + r] : 0.0;
+    const double tu = (FAM == FAM_TANH && own) ? tanh(u) : 0.0;
+    if (row) {
+      xs[gi][r] = u;
+      ts[gi][r] = tu;
+    }
+    wave_sync();
+    bool bad = own && !finite64(u);
 
     // ---- this lane's row of J (tangent) or of J^T (adjoint), in registers ----
     // entry (i, j) of J is dF_i/du_j, the forward-mode tangent of F_i for the
