@@ -583,9 +583,9 @@ int nls_get_mapping(const nls_context* c, int family, int n, int alg, int precis
   if (alg == ALG_POLY) alg = ALG_NEWTON;  // every stage of the chain runs on the Newton stage's mapping
   const bool rows2 = two_rows_ok(n, family, alg);
   // lanes per system of the group mapping with its default rows per lane (two
-  // in the FP64 form, one in the FP32-inner form, unless NLS_GROUP_ROWS says)
+  // in both forms, unless NLS_GROUP_ROWS says)
   const int env_rows = group_rows_env();
-  const int def_rows = (env_rows == 1 || env_rows == 2) ? env_rows : (precision == NLS_PREC_FP64 ? 2 : 1);
+  const int def_rows = (env_rows == 1 || env_rows == 2) ? env_rows : 2;
   const int group_l = n <= 16 ? (rows2 && def_rows == 2 ? 8 : 16) : (n <= 32 ? 32 : 64);
   if (n > 16) { *lanes_per_system = group_l; return NLS_OK; }
   if (n <= 8 && (family == FAM_PAPER || (family == FAM_ROSENBROCK && n < 2))) { *lanes_per_system = 1; return NLS_OK; }

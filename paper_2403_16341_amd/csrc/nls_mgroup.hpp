@@ -249,6 +249,16 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
 // butterfly combines those.  On return entry r L + q of the solution is in
 // x[r] (and the whole solution in sh.sol).  Returns false (group-uniform) on a
 // zero or non-finite pivot.
+// Lane of this lane's group whose bit is set in the wave-wide ballot b (the
+// lowest such lane; every group has one where this is used), as a lane index
+// of the wavefront.
+template <int L> __device__ __forceinline__ int mg_group_lane(unsigned long long b, int gi) {
+  const unsigned long long gbits = (L == 64) ? b : ((b >> (gi * L)) & ((1ull << L) - 1ull));
+  return gi * L + (int)__builtin_ctzll(gbits | (1ull << (L == 64 ? 63 : L)));
+}
+__device__ __forceinline__ double mg_shfl(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float mg_shfl(float v, int src) { return __shfl(v, src, 64); }
+
 template <int NB, int L, typename TI>
 __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int q, int n,
                                             TI (&J)[MGeom<NB, L>::R][NB], TI (&x)[MGeom<NB, L>::R]) {
@@ -296,65 +306,141 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         grp_levels<L>([&](auto mc) { pk = min(pk, grp_partner<decltype(mc)::value, L>(pk)); });
         owner = top && kp == pk;
       }
-      // the pivot row publishes columns k.. , its RHS and its position (the
-      // lane holding it picks the row by selects, so the rows stay in registers)
-      if (owner) {
+      if constexpr (sizeof(TI) == 4) {
+        // The pivot row, its right-hand side and its position come straight from
+        // the lane that holds them (a lane permute from the group's owner lane,
+        // no round trip through LDS): every lane picks its candidate row by
+        // selects, and the group reads the owner's.
+        const int src = mg_group_lane<L>(__ballot(owner), gi);
         int rsel = 0;
 #pragma unroll
         for (int r = 1; r < R; ++r) rsel = pos[r] == kp ? r : rsel;
-#pragma unroll
-        for (int j = k; j < NB; ++j) {
+        kp = __shfl(kp, src, 64);
+        auto cand = [&](int j) {
           TI v = J[0][j];
 #pragma unroll
           for (int r = 1; r < R; ++r) v = rsel == r ? J[r][j] : v;
-          sh.piv[gi][j] = v;
-        }
-        TI v = x[0];
+          return v;
+        };
+        const TI pv = mg_shfl(cand(k), src);
+        ok = ok && !nan_k && pv != TI(0) && fin(pv);
+        const TI rp = recip(pv);
+        TI l[R];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v = rsel == r ? x[r] : v;
-        sh.piv[gi][NB] = v;
-        sh.ppos[gi] = kp;
+        for (int r = 0; r < R; ++r) {
+          // exchange of logical positions k <-> kp
+          if (pos[r] == kp) {
+            rd[r] = rp;
+            pos[r] = k;
+          } else if (pos[r] == k) {
+            pos[r] = kp;
+          }
+          const bool upd = own[r] && pos[r] > k;
+          l[r] = upd ? J[r][k] * rp : TI(0);
+          if (upd) J[r][k] = l[r];
+        }
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+          const TI pj = mg_shfl(cand(j), src);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (own[r] && pos[r] > k) J[r][j] = fmat(-l[r], pj, J[r][j]);
+        }
+        {
+          TI xv = x[0];
+#pragma unroll
+          for (int r = 1; r < R; ++r) xv = rsel == r ? x[r] : xv;
+          const TI px = mg_shfl(xv, src);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (own[r] && pos[r] > k) x[r] = fmat(-l[r], px, x[r]);
+        }
+      } else {
+        // the pivot row publishes columns k.. , its RHS and its position (the
+        // lane holding it picks the row by selects, so the rows stay in registers)
+        if (owner) {
+          int rsel = 0;
+#pragma unroll
+          for (int r = 1; r < R; ++r) rsel = pos[r] == kp ? r : rsel;
+#pragma unroll
+          for (int j = k; j < NB; ++j) {
+            TI v = J[0][j];
+#pragma unroll
+            for (int r = 1; r < R; ++r) v = rsel == r ? J[r][j] : v;
+            sh.piv[gi][j] = v;
+          }
+          TI v = x[0];
+#pragma unroll
+          for (int r = 1; r < R; ++r) v = rsel == r ? x[r] : v;
+          sh.piv[gi][NB] = v;
+          sh.ppos[gi] = kp;
+        }
+        wave_sync();
+        kp = sh.ppos[gi];
+        const TI pv = sh.piv[gi][k];
+        ok = ok && !nan_k && pv != TI(0) && fin(pv);
+        const TI rp = recip(pv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          // exchange of logical positions k <-> kp
+          if (pos[r] == kp) {
+            rd[r] = rp;
+            pos[r] = k;
+          } else if (pos[r] == k) {
+            pos[r] = kp;
+          }
+          if (own[r] && pos[r] > k) {
+            const TI l = J[r][k] * rp;
+            J[r][k] = l;
+#pragma unroll
+            for (int j = k + 1; j < NB; ++j) J[r][j] = fmat(-l, sh.piv[gi][j], J[r][j]);
+            x[r] = fmat(-l, sh.piv[gi][NB], x[r]);
+          }
+        }
+        wave_sync();
       }
-      wave_sync();
-      kp = sh.ppos[gi];
-      const TI pv = sh.piv[gi][k];
-      ok = ok && !nan_k && pv != TI(0) && fin(pv);
-      const TI rp = recip(pv);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        // exchange of logical positions k <-> kp
-        if (pos[r] == kp) {
-          rd[r] = rp;
-          pos[r] = k;
-        } else if (pos[r] == k) {
-          pos[r] = kp;
-        }
-        if (own[r] && pos[r] > k) {
-          const TI l = J[r][k] * rp;
-          J[r][k] = l;
-#pragma unroll
-          for (int j = k + 1; j < NB; ++j) J[r][j] = fmat(-l, sh.piv[gi][j], J[r][j]);
-          x[r] = fmat(-l, sh.piv[gi][NB], x[r]);
-        }
-      }
-      wave_sync();
     }
   });
-  // back substitution, column by column from the last
-  static_for<0, NB>([&](auto kc) {
-    constexpr int k = NB - 1 - decltype(kc)::value;
-    if (k < n) {
+  if constexpr (sizeof(TI) == 4) {
+    // back substitution, column by column from the last: the lane holding
+    // logical position k computes x_k, the group takes it by a lane permute, and
+    // the owner also stores it for the gather below
+    static_for<0, NB>([&](auto kc) {
+      constexpr int k = NB - 1 - decltype(kc)::value;
+      if (k < n) {
+        bool has = false;
+        TI xl = TI(0);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (pos[r] == k) sh.sol[gi][k] = x[r] * rd[r];
-      wave_sync();
-      const TI xk = sh.sol[gi][k];
+        for (int r = 0; r < R; ++r) {
+          const bool h = pos[r] == k;
+          xl = h ? x[r] * rd[r] : xl;
+          has = has || h;
+        }
+        const TI xk = mg_shfl(xl, mg_group_lane<L>(__ballot(has), gi));
+        if (has) sh.sol[gi][k] = xk;
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (own[r] && pos[r] < k) x[r] = fmat(-J[r][k], xk, x[r]);
-      wave_sync();
-    }
-  });
+        for (int r = 0; r < R; ++r)
+          if (own[r] && pos[r] < k) x[r] = fmat(-J[r][k], xk, x[r]);
+      }
+    });
+    wave_sync();
+  } else {
+    // back substitution, column by column from the last
+    static_for<0, NB>([&](auto kc) {
+      constexpr int k = NB - 1 - decltype(kc)::value;
+      if (k < n) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (pos[r] == k) sh.sol[gi][k] = x[r] * rd[r];
+        wave_sync();
+        const TI xk = sh.sol[gi][k];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (own[r] && pos[r] < k) x[r] = fmat(-J[r][k], xk, x[r]);
+        wave_sync();
+      }
+    });
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) x[r] = own[r] ? sh.sol[gi][r * L + q] : TI(0);
   wave_sync();
