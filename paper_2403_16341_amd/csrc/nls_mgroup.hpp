@@ -291,6 +291,27 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         key = take ? kr : key;
         kp = take ? pos[r] : kp;
       }
+      if constexpr (sizeof(TI) == 8) {
+        // every lane writes its candidate row (the local best) and RHS to a
+        // slot of its own while the group search runs; the owner's slot is
+        // read below (the column-sum area is free during the factorisation)
+        int rs = 0;
+#pragma unroll
+        for (int r = 1; r < R; ++r) rs = pos[r] == kp ? r : rs;
+        static_assert(sizeof(sh.cs) >= 64 * (NB + 2) * sizeof(TI), "a slot per lane in the column-sum area");
+        TI* slot = reinterpret_cast<TI*>(&sh.cs[0][0]) + threadIdx.x * (NB + 2);
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+          TI v = J[0][j];
+#pragma unroll
+          for (int r = 1; r < R; ++r) v = rs == r ? J[r][j] : v;
+          slot[j] = v;
+        }
+        TI v = x[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v = rs == r ? x[r] : v;
+        slot[NB] = v;
+      }
       nan_k = grp_any<L>(nan_k);
       // The group's largest key, then the lane holding it.  Usually one lane
       // does: it publishes its row and position.  When several hold the
@@ -356,28 +377,21 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
             if (own[r] && pos[r] > k) x[r] = fmat(-l[r], px, x[r]);
         }
       } else {
-        // the pivot row publishes columns k.. , its RHS and its position (the
-        // lane holding it picks the row by selects, so the rows stay in registers)
-        if (owner) {
-          int rsel = 0;
+        // The pivot and its position come from the owner lane by a lane
+        // permute, so that the reciprocal can start at once; the rest of the
+        // pivot row and its RHS are published through LDS (the lane holding
+        // the row picks it by selects, so the rows stay in registers).
+        int rsel = 0;
 #pragma unroll
-          for (int r = 1; r < R; ++r) rsel = pos[r] == kp ? r : rsel;
+        for (int r = 1; r < R; ++r) rsel = pos[r] == kp ? r : rsel;
+        TI pl = J[0][k];
 #pragma unroll
-          for (int j = k; j < NB; ++j) {
-            TI v = J[0][j];
-#pragma unroll
-            for (int r = 1; r < R; ++r) v = rsel == r ? J[r][j] : v;
-            sh.piv[gi][j] = v;
-          }
-          TI v = x[0];
-#pragma unroll
-          for (int r = 1; r < R; ++r) v = rsel == r ? x[r] : v;
-          sh.piv[gi][NB] = v;
-          sh.ppos[gi] = kp;
-        }
+        for (int r = 1; r < R; ++r) pl = rsel == r ? J[r][k] : pl;
+        const int src = mg_group_lane<L>(__ballot(owner), gi);
+        const TI pv = mg_shfl(pl, src);
+        kp = __shfl(kp, src, 64);
+        const TI* prow = reinterpret_cast<const TI*>(&sh.cs[0][0]) + src * (NB + 2);
         wave_sync();
-        kp = sh.ppos[gi];
-        const TI pv = sh.piv[gi][k];
         ok = ok && !nan_k && pv != TI(0) && fin(pv);
         const TI rp = recip(pv);
 #pragma unroll
@@ -393,8 +407,8 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
             const TI l = J[r][k] * rp;
             J[r][k] = l;
 #pragma unroll
-            for (int j = k + 1; j < NB; ++j) J[r][j] = fmat(-l, sh.piv[gi][j], J[r][j]);
-            x[r] = fmat(-l, sh.piv[gi][NB], x[r]);
+            for (int j = k + 1; j < NB; ++j) J[r][j] = fmat(-l, prow[j], J[r][j]);
+            x[r] = fmat(-l, prow[NB], x[r]);
           }
         }
         wave_sync();
