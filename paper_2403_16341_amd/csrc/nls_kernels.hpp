@@ -1178,6 +1178,15 @@ __device__ __forceinline__ int wave_lane_of(bool pred) { return __builtin_ctzll(
 
 // Back substitution over the kept factors, column by column from the last;
 // on return component k of the solution is in sh.sol[gi][k].
+// Lane of the wavefront holding the lowest bit of the ballot b that falls in
+// this lane's group of L lanes (every group has one where this is used).
+template <int L> __device__ __forceinline__ int group_lane_of(unsigned long long b, int gi) {
+  const unsigned long long gbits = (L == 64) ? b : ((b >> (gi * L)) & ((1ull << L) - 1ull));
+  return gi * L + (int)__builtin_ctzll(gbits | (1ull << (L == 64 ? 63 : L)));
+}
+__device__ __forceinline__ double lane_shfl(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, src, 64); }
+
 template <int NB, int L, typename TI>
 __device__ __forceinline__ void group_back_substitute(GroupShared<NB, L, TI>& sh, int gi, int r, int n,
                                                       const TI (&J)[NB], int pos, TI myrd, TI rhs) {
@@ -1188,6 +1197,20 @@ __device__ __forceinline__ void group_back_substitute(GroupShared<NB, L, TI>& sh
     for (int k = NB - 1; k >= 0; --k) {
       if (k < n) {
         const TI xk = wave_bcast(rhs * myrd, wave_lane_of(pos == k));
+        if (r == k) mine = xk;
+        if (own && pos < k) rhs = fmat(-J[k], xk, rhs);
+      }
+    }
+    if (own) sh.sol[gi][r] = mine;
+    wave_sync();
+  } else if constexpr (sizeof(TI) == 4) {
+    // FP32: each solution component comes from the lane holding its position
+    // by a lane permute (one per component) instead of an LDS round trip
+    TI mine = TI(0);
+#pragma unroll
+    for (int k = NB - 1; k >= 0; --k) {
+      if (k < n) {
+        const TI xk = lane_shfl(rhs * myrd, group_lane_of<L>(__ballot(pos == k), gi));
         if (r == k) mine = xk;
         if (own && pos < k) rhs = fmat(-J[k], xk, rhs);
       }
@@ -1262,6 +1285,27 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
 #pragma unroll
         for (int j = k + 1; j < NB; ++j) {
           const TI pj = wave_bcast(J[j], pl);  // read before this step changes any row
+          if (upd) J[j] = fmat(-l, pj, J[j]);
+        }
+        if (upd) rhs = fmat(-l, prhs, rhs);
+      } else if constexpr (sizeof(TI) == 4) {
+        // FP32: the pivot row's columns k.., RHS and position come from its
+        // lane by lane permutes (one per 32-bit word), with no LDS round trip
+        const int src = group_lane_of<L>(__ballot(owner), gi);
+        const int kp = __shfl(pos, src, 64);
+        const TI pv = lane_shfl(J[k], src);
+        const TI prhs = lane_shfl(rhs, src);
+        ok = ok && !nan_at_k && pv != TI(0) && fin(pv);
+        const TI rp = recip(pv);
+        if (pos == kp) myrd = rp;
+        if (pos == kp) pos = k;
+        else if (pos == k) pos = kp;
+        const bool upd = own && pos > k;
+        const TI l = J[k] * rp;
+        if (upd) J[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+          const TI pj = lane_shfl(J[j], src);  // read before this step changes any row
           if (upd) J[j] = fmat(-l, pj, J[j]);
         }
         if (upd) rhs = fmat(-l, prhs, rhs);

@@ -249,16 +249,6 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
 // butterfly combines those.  On return entry r L + q of the solution is in
 // x[r] (and the whole solution in sh.sol).  Returns false (group-uniform) on a
 // zero or non-finite pivot.
-// Lane of this lane's group whose bit is set in the wave-wide ballot b (the
-// lowest such lane; every group has one where this is used), as a lane index
-// of the wavefront.
-template <int L> __device__ __forceinline__ int mg_group_lane(unsigned long long b, int gi) {
-  const unsigned long long gbits = (L == 64) ? b : ((b >> (gi * L)) & ((1ull << L) - 1ull));
-  return gi * L + (int)__builtin_ctzll(gbits | (1ull << (L == 64 ? 63 : L)));
-}
-__device__ __forceinline__ double mg_shfl(double v, int src) { return __shfl(v, src, 64); }
-__device__ __forceinline__ float mg_shfl(float v, int src) { return __shfl(v, src, 64); }
-
 template <int NB, int L, typename TI>
 __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int q, int n,
                                             TI (&J)[MGeom<NB, L>::R][NB], TI (&x)[MGeom<NB, L>::R]) {
@@ -332,7 +322,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         // the lane that holds them (a lane permute from the group's owner lane,
         // no round trip through LDS): every lane picks its candidate row by
         // selects, and the group reads the owner's.
-        const int src = mg_group_lane<L>(__ballot(owner), gi);
+        const int src = group_lane_of<L>(__ballot(owner), gi);
         int rsel = 0;
 #pragma unroll
         for (int r = 1; r < R; ++r) rsel = pos[r] == kp ? r : rsel;
@@ -343,7 +333,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
           for (int r = 1; r < R; ++r) v = rsel == r ? J[r][j] : v;
           return v;
         };
-        const TI pv = mg_shfl(cand(k), src);
+        const TI pv = lane_shfl(cand(k), src);
         ok = ok && !nan_k && pv != TI(0) && fin(pv);
         const TI rp = recip(pv);
         TI l[R];
@@ -362,7 +352,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         }
 #pragma unroll
         for (int j = k + 1; j < NB; ++j) {
-          const TI pj = mg_shfl(cand(j), src);
+          const TI pj = lane_shfl(cand(j), src);
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (own[r] && pos[r] > k) J[r][j] = fmat(-l[r], pj, J[r][j]);
@@ -371,7 +361,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
           TI xv = x[0];
 #pragma unroll
           for (int r = 1; r < R; ++r) xv = rsel == r ? x[r] : xv;
-          const TI px = mg_shfl(xv, src);
+          const TI px = lane_shfl(xv, src);
 #pragma unroll
           for (int r = 0; r < R; ++r)
             if (own[r] && pos[r] > k) x[r] = fmat(-l[r], px, x[r]);
@@ -387,8 +377,8 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
         TI pl = J[0][k];
 #pragma unroll
         for (int r = 1; r < R; ++r) pl = rsel == r ? J[r][k] : pl;
-        const int src = mg_group_lane<L>(__ballot(owner), gi);
-        const TI pv = mg_shfl(pl, src);
+        const int src = group_lane_of<L>(__ballot(owner), gi);
+        const TI pv = lane_shfl(pl, src);
         kp = __shfl(kp, src, 64);
         const TI* prow = reinterpret_cast<const TI*>(&sh.cs[0][0]) + src * (NB + 2);
         wave_sync();
@@ -430,7 +420,7 @@ __device__ __forceinline__ bool mg_lu_solve(MShared<NB, L, TI>& sh, int gi, int 
           xl = h ? x[r] * rd[r] : xl;
           has = has || h;
         }
-        const TI xk = mg_shfl(xl, mg_group_lane<L>(__ballot(has), gi));
+        const TI xk = lane_shfl(xl, group_lane_of<L>(__ballot(has), gi));
         if (has) sh.sol[gi][k] = xk;
 #pragma unroll
         for (int r = 0; r < R; ++r)
