@@ -43,9 +43,9 @@ template <int NB, int L, typename TI> struct MShared {
   static constexpr int CS_GRP = L * CS_ROW + 8;
   double x[G][RS];      // evaluation point (cubic) or its column map tanh(x) (tanh)
   double dphi[G][RS];   // dual derivative of the column map at the iterate (tanh)
-  double cs[G][CS_GRP]; // per-lane column sums sum_r A_{r L + q, j} F_{r L + q}
-  TI piv[G][NB + 2];    // pivot row of the current elimination step (columns k..) and its RHS
-  int ppos[G];          // the pivot row's logical position
+  // per-lane column sums sum_r A_{r L + q, j} F_{r L + q}; during an FP64
+  // factorisation, each lane's candidate pivot row (a slot of NB + 2 per lane)
+  double cs[G][CS_GRP];
   TI sol[G][RS];        // solution of the triangular solves
   TI gv[G][RS];         // g = J^T F
   TI jg[G][RS];         // J g

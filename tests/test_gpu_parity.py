@@ -107,6 +107,38 @@ def test_edge_families_and_cases(nls, ctx):
                 u_tol="bound" if b.name in ("rosenbrock", "paper-example") else "strict")
 
 
+@pytest.mark.parametrize("n", [4, 8, 16, 32])
+def test_pivot_ties(nls, ctx, n):
+    """Exact ties among the pivot candidates at every elimination step: cubic
+    systems whose matrix is a Hadamard matrix (entries +-1, rows permuted and
+    rows and columns sign-flipped at random), solved from u0 = 0, where the
+    first Jacobian is the matrix itself; its elimination keeps producing
+    columns of equal magnitudes.  The first maximum in current row order must
+    win in every mapping (lane at n = 4 and 8, two rows per lane at 16, one
+    row per lane at 32): FP64 meets the parity bar against the oracle, and the
+    FP32-inner form keeps the FP64 stopping test on every success."""
+    rng = np.random.Generator(np.random.PCG64(4100 + n))
+    M = 200
+    H = np.array([[1.0]])
+    while H.shape[0] < n:
+        H = np.block([[H, H], [H, -H]])
+    A = np.empty((M, n, n))
+    for m in range(M):
+        perm, s1, s2 = rng.permutation(n), rng.choice([-1.0, 1.0], n), rng.choice([-1.0, 1.0], n)
+        A[m] = s1[:, None] * H[perm] * s2[None, :]
+    b = rng.integers(-3, 4, (M, n)).astype(np.float64)
+    p = np.concatenate([A.reshape(M, n * n), b], axis=1)
+    for alg in (inputs.NEWTON, inputs.ARMIJO):
+        bt = inputs.homogeneous(inputs.CUBIC, n, alg, p, np.zeros((M, n)), 1e-10, 40, name="pivot-ties")
+        print("case: pivot ties n=%d alg=%d" % (n, alg), flush=True)
+        compare(bt, run_gpu(nls, ctx, bt), "ties-n%d-alg%d" % (n, alg))
+        g32 = run_gpu(nls, ctx, bt, precision=inputs.PREC_FP32_INNER)
+        assert (g32["retcode"] != nls.RC_INVALID).all()
+        succ = g32["retcode"] == oracle.RC_SUCCESS
+        assert succ.mean() >= 0.95
+        assert (g32["fnorm_inf"][succ] <= bt.abstol).all()
+
+
 def test_paper_gpu_workload(nls, ctx):
     """The batch of the paper's GPU kernel example (Sec. 3.3): 1,024 x
     generalized Rosenbrock N = 10 from U(0,1)^10, Newton; every system reaches
