@@ -303,7 +303,7 @@ def serving_leg(nls, args):
     pool = inputs.serving_requests(args.serve_payloads, rate_hz=1.0, precision=inputs.PREC_FP32_INNER)
     print("[bench] serving: %d request payloads generated (%.1f s), %d systems"
           % (len(pool), time.perf_counter() - t0, sum(r.batch.M for r in pool)), file=sys.stderr, flush=True)
-    srv = nls.Server(0, mem_budget_bytes=args.serve_budget_gib << 30, streams=4)
+    srv = nls.Server(0, mem_budget_bytes=args.serve_budget_gib << 30, streams=args.serve_streams)
     keys = ("u", "fnorm_inf", "iters", "retcode", "nfev", "njev")
 
     # closed loop: capacity, and the per-payload reference results
@@ -318,7 +318,7 @@ def serving_leg(nls, args):
         conv += int((out["retcode"] == 0).sum())
     cap_rps = len(pool) / wall
     res = {"payloads": len(pool), "systems": int(sum(r.batch.M for r in pool)),
-           "budget_bytes": srv.stats()["budget_bytes"], "streams": 4,
+           "budget_bytes": srv.stats()["budget_bytes"], "streams": args.serve_streams,
            "closed_loop": {"wall_s": wall, "requests_per_s": cap_rps, "converged": conv,
                            "solves_per_s": conv / wall}}
     print("[bench] serving closed loop: %.2f s, %.2f req/s, %.0f solves/s"
@@ -354,10 +354,12 @@ def serving_leg(nls, args):
         sizes = np.array([i["systems"] for i, _ in infos])
         lat = np.array(lat)
         small = lat[sizes <= 256]
+        small_queue = np.array(queue)[sizes <= 256]
         e = {"load": frac, "rate_hz": rate, "requests": R, "wall_s": wall,
              "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": float(lat.max()),
              "p50_small_ms": _pct(small, 50), "p99_small_ms": _pct(small, 99),
              "p50_queue_ms": _pct(queue, 50), "p99_queue_ms": _pct(queue, 99),
+             "p99_small_queue_ms": _pct(small_queue, 99),
              "mean_merged": float(np.mean([i["merged"] for i, _ in infos])),
              "converged": conv, "solves_per_s": conv / wall}
         res["open_loop"].append(e)
@@ -376,7 +378,7 @@ def leg_cmd(leg, args):
            "--steps", str(args.steps), "--warmup", str(args.warmup), "--systems", str(args.systems),
            "--serve-payloads", str(args.serve_payloads), "--serve-stream", str(args.serve_stream),
            "--serve-load", ",".join(str(x) for x in args.serve_load),
-           "--serve-budget-gib", str(args.serve_budget_gib)]
+           "--serve-budget-gib", str(args.serve_budget_gib), "--serve-streams", str(args.serve_streams)]
     if args.parity_dir:
         cmd += ["--parity-dir", args.parity_dir]
     return cmd
@@ -700,6 +702,7 @@ def main():
     ap.add_argument("--serve-load", type=lambda x: [float(v) for v in x.split(",")], default=[0.5, 0.8],
                     help="open-loop arrival rates as fractions of the closed-loop capacity")
     ap.add_argument("--serve-budget-gib", type=int, default=8, help="server device-memory budget")
+    ap.add_argument("--serve-streams", type=int, default=4, help="server streams (stream 0 for small launches)")
     ap.add_argument("--leg", choices=("headline", "extras", "serving", "oracle"), default=None,
                     help="run one leg in this process and print its JSON")
     ap.add_argument("--forms", default=None, help="profiling: time only this form (fp64 or fp32) in-process")

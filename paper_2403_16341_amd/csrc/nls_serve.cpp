@@ -10,17 +10,25 @@
 //     host-to-device copy of the inputs, the work-counter reset, the
 //     persistent solver launch and one device-to-host copy of the outputs,
 //     then an event.
+// Launches whose inputs or results take more than a few MiB of host copies
+// hand those copies, split by systems, to a small pool of copy threads, so
+// that one large request does not hold up the reaping and admission of the
+// others while its megabytes move; the launch is enqueued once its inputs
+// are staged, and completed once its results are in the callers' arrays.
 // Everything the device touches lives in the arena (allocated once at
 // creation), so admission and completion never call hipMalloc or hipFree.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -50,6 +58,8 @@ struct Req {
   double t_submit = 0.0, t_admit = 0.0;
 };
 
+enum Phase { PH_STAGING, PH_DEVICE, PH_SCATTER };
+
 struct InFlight {
   PlannedLaunch plan;
   std::vector<Req> reqs;  // in the order of plan.reqs
@@ -57,7 +67,17 @@ struct InFlight {
   int stream = 0;
   int counter = 0;
   int32_t status = NLS_OK;
+  Phase phase = PH_DEVICE;
+  // copy jobs of the current phase not yet finished (copy threads decrement)
+  std::shared_ptr<std::atomic<int>> pending = std::make_shared<std::atomic<int>>(0);
 };
+
+// host copies of a launch above this size go to the copy threads, in jobs of
+// about kCopyJobBytes each (NLS_SERVE_INLINE_COPY_BYTES and
+// NLS_SERVE_COPY_JOB_BYTES, read at creation, override them)
+constexpr size_t kInlineCopyBytes = size_t(4) << 20;
+constexpr size_t kCopyJobBytes = size_t(16) << 20;
+constexpr int kCopyThreads = 4;
 
 }  // namespace
 
@@ -67,6 +87,8 @@ struct nls_server {
   int max_inflight = 256;
   int max_admit = 256;
   double slice_work = 0.0;  // no slicing unless NLS_SERVE_SLICE_WORK > 0
+  size_t inline_copy_bytes = kInlineCopyBytes;
+  size_t copy_job_bytes = kCopyJobBytes;
   std::vector<hipStream_t> streams;
   std::vector<double> load;  // estimated outstanding work per stream
   char* dev = nullptr;       // device arena
@@ -78,6 +100,13 @@ struct nls_server {
   Clock::time_point t0;
   std::list<InFlight> inflight;  // scheduler thread only
   std::thread th;
+
+  // copy threads and their job queue, under cmu
+  std::vector<std::thread> copiers;
+  std::mutex cmu;
+  std::condition_variable ccv;
+  std::deque<std::function<void()>> cjobs;
+  bool cstop = false;
 
   // shared with client threads, under mu
   std::mutex mu;
@@ -112,34 +141,94 @@ std::string merge_key(const Req& q) {
   return k;
 }
 
-// copy a request's inputs into the pinned mirror of its launch region
-void stage_inputs(nls_server* s, const InFlight& L, const Req& q, int64_t first) {
+// copy systems [i0, i1) of a request's inputs into the pinned mirror of its
+// launch region
+void stage_inputs(nls_server* s, const InFlight& L, const Req& q, int64_t first, int64_t i0, int64_t i1) {
   char* base = s->host + L.plan.offset;
   double* P = (double*)(base + L.plan.layout.params) + first * q.P;
   double* U = (double*)(base + L.plan.layout.u0) + first * q.n;
   if (q.P > 0) {
-    if (!q.b.p_offset) std::memcpy(P, q.b.params, sizeof(double) * q.M * q.P);
+    if (!q.b.p_offset) std::memcpy(P + i0 * q.P, q.b.params + i0 * q.P, sizeof(double) * (i1 - i0) * q.P);
     else
-      for (int64_t i = 0; i < q.M; ++i) std::memcpy(P + i * q.P, q.b.params + q.b.p_offset[i], sizeof(double) * q.P);
+      for (int64_t i = i0; i < i1; ++i) std::memcpy(P + i * q.P, q.b.params + q.b.p_offset[i], sizeof(double) * q.P);
   }
-  if (!q.b.u_offset) std::memcpy(U, q.b.u0, sizeof(double) * q.M * q.n);
+  if (!q.b.u_offset) std::memcpy(U + i0 * q.n, q.b.u0 + i0 * q.n, sizeof(double) * (i1 - i0) * q.n);
   else
-    for (int64_t i = 0; i < q.M; ++i) std::memcpy(U + i * q.n, q.b.u0 + q.b.u_offset[i], sizeof(double) * q.n);
+    for (int64_t i = i0; i < i1; ++i) std::memcpy(U + i * q.n, q.b.u0 + q.b.u_offset[i], sizeof(double) * q.n);
 }
 
-// copy a request's outputs from the pinned mirror into the caller's arrays
-void scatter_results(nls_server* s, const InFlight& L, const Req& q, int64_t first) {
+// copy systems [i0, i1) of a request's outputs from the pinned mirror into
+// the caller's arrays
+void scatter_results(nls_server* s, const InFlight& L, const Req& q, int64_t first, int64_t i0, int64_t i1) {
   const char* base = s->host + L.plan.offset;
   const Region& g = L.plan.layout;
   const double* u = (const double*)(base + g.u) + first * q.n;
-  if (!q.b.u_offset) std::memcpy(q.r.u, u, sizeof(double) * q.M * q.n);
+  const int64_t k = i1 - i0;
+  if (!q.b.u_offset) std::memcpy(q.r.u + i0 * q.n, u + i0 * q.n, sizeof(double) * k * q.n);
   else
-    for (int64_t i = 0; i < q.M; ++i) std::memcpy(q.r.u + q.b.u_offset[i], u + i * q.n, sizeof(double) * q.n);
-  std::memcpy(q.r.fnorm_inf, (const double*)(base + g.fnorm) + first, sizeof(double) * q.M);
-  std::memcpy(q.r.iters, (const int32_t*)(base + g.iters) + first, sizeof(int32_t) * q.M);
-  std::memcpy(q.r.retcode, (const int32_t*)(base + g.retcode) + first, sizeof(int32_t) * q.M);
-  if (q.r.nfev) std::memcpy(q.r.nfev, (const int32_t*)(base + g.nfev) + first, sizeof(int32_t) * q.M);
-  if (q.r.njev) std::memcpy(q.r.njev, (const int32_t*)(base + g.njev) + first, sizeof(int32_t) * q.M);
+    for (int64_t i = i0; i < i1; ++i) std::memcpy(q.r.u + q.b.u_offset[i], u + i * q.n, sizeof(double) * q.n);
+  first += i0;
+  std::memcpy(q.r.fnorm_inf + i0, (const double*)(base + g.fnorm) + first, sizeof(double) * k);
+  std::memcpy(q.r.iters + i0, (const int32_t*)(base + g.iters) + first, sizeof(int32_t) * k);
+  std::memcpy(q.r.retcode + i0, (const int32_t*)(base + g.retcode) + first, sizeof(int32_t) * k);
+  if (q.r.nfev) std::memcpy(q.r.nfev + i0, (const int32_t*)(base + g.nfev) + first, sizeof(int32_t) * k);
+  if (q.r.njev) std::memcpy(q.r.njev + i0, (const int32_t*)(base + g.njev) + first, sizeof(int32_t) * k);
+}
+
+size_t input_bytes_per_system(const Req& q) { return sizeof(double) * (size_t)(q.P + q.n); }
+size_t result_bytes_per_system(const Req& q) { return sizeof(double) * (size_t)(q.n + 1) + 4 * sizeof(int32_t); }
+
+// run copy(L, q, first, i0, i1) over every request of launch L: inline when
+// the launch's bytes are few, else as jobs of the copy threads (L.pending
+// counts them down; the scheduler polls it).  Returns true if done inline.
+template <typename Copy>
+bool run_copies(nls_server* s, InFlight& L, size_t (*bytes_per_system)(const Req&), Copy copy) {
+  size_t total = 0;
+  for (const Req& q : L.reqs) total += bytes_per_system(q) * (size_t)q.M;
+  if (total <= s->inline_copy_bytes || s->copiers.empty()) {
+    for (size_t j = 0; j < L.reqs.size(); ++j) copy(s, L, L.reqs[j], L.plan.first[j], int64_t(0), L.reqs[j].M);
+    return true;
+  }
+  std::vector<std::function<void()>> jobs;
+  for (size_t j = 0; j < L.reqs.size(); ++j) {
+    const Req& q = L.reqs[j];
+    const int64_t step = std::max<int64_t>(1, (int64_t)(s->copy_job_bytes / bytes_per_system(q)));
+    const int64_t first = L.plan.first[j];
+    for (int64_t i0 = 0; i0 < q.M; i0 += step) {
+      const int64_t i1 = std::min<int64_t>(q.M, i0 + step);
+      InFlight* lp = &L;
+      const Req* qp = &q;
+      jobs.push_back([s, lp, qp, first, i0, i1, copy] {
+        copy(s, *lp, *qp, first, i0, i1);
+        if (lp->pending->fetch_sub(1) == 1) {
+          // the last job of the phase: wake the scheduler
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->cv_work.notify_all();
+        }
+      });
+    }
+  }
+  L.pending->store((int)jobs.size());
+  {
+    std::lock_guard<std::mutex> lk(s->cmu);
+    for (auto& f : jobs) s->cjobs.push_back(std::move(f));
+  }
+  s->ccv.notify_all();
+  return false;
+}
+
+void copier(nls_server* s) {
+  while (true) {
+    std::function<void()> job;
+    {
+      std::unique_lock<std::mutex> lk(s->cmu);
+      s->ccv.wait(lk, [&] { return s->cstop || !s->cjobs.empty(); });
+      if (s->cjobs.empty()) return;  // stopping, nothing left
+      job = std::move(s->cjobs.front());
+      s->cjobs.pop_front();
+    }
+    job();
+  }
 }
 
 // enqueue one launch: inputs in, counter reset, solve, outputs out, event
@@ -192,9 +281,9 @@ int32_t enqueue(nls_server* s, InFlight& L) {
   return NLS_OK;
 }
 
+// release a launch whose results are in the callers' arrays (or that failed)
+// and report its requests
 void complete(nls_server* s, InFlight& L) {
-  if (L.status == NLS_OK)
-    for (size_t j = 0; j < L.reqs.size(); ++j) scatter_results(s, L, L.reqs[j], L.plan.first[j]);
   const double t = s->now_ms();
   s->arena.release(L.plan.offset, L.plan.layout.total);
   s->free_counters.push_back(L.counter);
@@ -219,18 +308,50 @@ void complete(nls_server* s, InFlight& L) {
   s->cv_done.notify_all();
 }
 
+// a launch failed to enqueue: wait for what was enqueued for it, then report
+void fail_launch(nls_server* s, InFlight& L) {
+  hipStreamSynchronize(s->streams[L.stream]);
+  complete(s, L);
+}
+
+// move launch L on when its current phase has ended; true when L is done
+bool advance(nls_server* s, InFlight& L) {
+  if (L.phase == PH_STAGING) {
+    if (L.pending->load() != 0) return false;
+    L.status = enqueue(s, L);
+    if (L.status != NLS_OK) {
+      fail_launch(s, L);
+      return true;
+    }
+    L.phase = PH_DEVICE;
+  }
+  if (L.phase == PH_DEVICE) {
+    const hipError_t e = hipEventQuery(L.ev);
+    if (e == hipErrorNotReady) return false;
+    if (e != hipSuccess) L.status = NLS_E_DEVICE;
+    if (L.status != NLS_OK || run_copies(s, L, result_bytes_per_system, scatter_results)) {
+      complete(s, L);
+      return true;
+    }
+    L.phase = PH_SCATTER;
+    return false;
+  }
+  if (L.pending->load() != 0) return false;
+  complete(s, L);
+  return true;
+}
+
 bool reap(nls_server* s) {
   bool any = false;
   for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-    const hipError_t e = hipEventQuery(it->ev);
-    if (e == hipErrorNotReady) {
-      ++it;
+    const Phase ph = it->phase;
+    if (advance(s, *it)) {
+      it = s->inflight.erase(it);
+      any = true;
       continue;
     }
-    if (e != hipSuccess) it->status = NLS_E_DEVICE;
-    complete(s, *it);
-    it = s->inflight.erase(it);
-    any = true;
+    any = any || it->phase != ph;
+    ++it;
   }
   return any;
 }
@@ -277,9 +398,7 @@ bool admit(nls_server* s) {
     } else if (hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) {
       L.ev = nullptr;
     }
-    for (size_t j = 0; j < L.reqs.size(); ++j) stage_inputs(s, L, L.reqs[j], P.first[j]);
     for (Req& q : L.reqs) q.t_admit = t_admit;
-    L.status = L.ev ? enqueue(s, L) : NLS_E_DEVICE;
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->st.launches += 1;
@@ -287,13 +406,23 @@ bool admit(nls_server* s) {
       s->st.resident_bytes = s->arena.used();
       s->st.peak_resident_bytes = std::max(s->st.peak_resident_bytes, s->st.resident_bytes);
     }
-    if (L.status != NLS_OK) {
-      // nothing (more) was enqueued for it: wait for what was, then report
-      hipStreamSynchronize(s->streams[L.stream]);
+    if (!L.ev) {
+      L.status = NLS_E_DEVICE;
       complete(s, L);
       continue;
     }
+    // (the list node stays put while copy jobs refer to it)
     s->inflight.push_back(std::move(L));
+    InFlight& R = s->inflight.back();
+    if (!run_copies(s, R, input_bytes_per_system, stage_inputs)) {
+      R.phase = PH_STAGING;
+      continue;
+    }
+    R.status = enqueue(s, R);
+    if (R.status != NLS_OK) {
+      fail_launch(s, R);
+      s->inflight.pop_back();
+    }
   }
   return true;
 }
@@ -317,6 +446,13 @@ void run(nls_server* s) {
 }
 
 void free_server(nls_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->cmu);
+    s->cstop = true;
+  }
+  s->ccv.notify_all();
+  for (auto& t : s->copiers)
+    if (t.joinable()) t.join();
   hipSetDevice(s->device);
   for (auto st : s->streams)
     if (st) hipStreamSynchronize(st);
@@ -357,6 +493,14 @@ int nls_server_create(const nls_server_desc* d, nls_server** out) {
     const double v = std::atof(w);
     if (v > 0) s->slice_work = v;
   }
+  if (const char* w = std::getenv("NLS_SERVE_INLINE_COPY_BYTES")) {
+    const long long v = std::atoll(w);
+    if (v >= 0) s->inline_copy_bytes = (size_t)v;
+  }
+  if (const char* w = std::getenv("NLS_SERVE_COPY_JOB_BYTES")) {
+    const long long v = std::atoll(w);
+    if (v > 0) s->copy_job_bytes = (size_t)v;
+  }
   s->arena.reset(d->mem_budget_bytes);
   s->st.budget_bytes = s->arena.capacity();
   s->t0 = Clock::now();
@@ -372,6 +516,7 @@ int nls_server_create(const nls_server_desc* d, nls_server** out) {
     return sfail(e == hipErrorOutOfMemory ? NLS_E_NOMEM : NLS_E_DEVICE, m);
   }
   for (int i = max_inflight - 1; i >= 0; --i) s->free_counters.push_back(i);
+  for (int j = 0; j < kCopyThreads; ++j) s->copiers.emplace_back(copier, s);
   s->th = std::thread(run, s);
   *out = s;
   return NLS_OK;

@@ -263,3 +263,62 @@ def test_server_fallback_chain_requests_match_the_batch_path(nls):
         assert _same(out, ref[ids[info["id"]]])
     # the chain did run past its Newton stage somewhere
     assert any((r["nfev"] > r["iters"] + 1).any() for r in ref)
+
+
+def _with_gaps(b, pg, ug):
+    """The same batch with pg unused doubles after each system's parameters
+    and ug after each starting point (NaN / 9.0 in the gaps)."""
+    p_off = b.p_off + pg * np.arange(b.M + 1, dtype=np.int64)
+    u_off = b.u_off + ug * np.arange(b.M + 1, dtype=np.int64)
+    params = np.full(p_off[-1], np.nan)
+    u0 = np.full(u_off[-1], 9.0)
+    for s in range(b.M):
+        P = b.p_off[s + 1] - b.p_off[s]
+        params[p_off[s]:p_off[s] + P] = b.params[b.p_off[s]:b.p_off[s + 1]]
+        u0[u_off[s]:u_off[s] + b.n[s]] = b.u0[b.u_off[s]:b.u_off[s + 1]]
+    return inputs.Batch(b.family, b.n, b.alg, params, p_off, u0, u_off, b.abstol, b.maxiters), u_off
+
+
+def test_server_copy_threads(nls, requests, monkeypatch):
+    """Host copies handed to the copy threads (thresholds lowered through
+    NLS_SERVE_INLINE_COPY_BYTES / NLS_SERVE_COPY_JOB_BYTES, read at server
+    creation, so that every launch is staged and scattered in several jobs
+    with a ragged last one): results bitwise those of the inline copies, for
+    contiguous requests and for requests with gaps between systems, merged
+    and alone."""
+    monkeypatch.setenv("NLS_SERVE_INLINE_COPY_BYTES", "0")
+    monkeypatch.setenv("NLS_SERVE_COPY_JOB_BYTES", "3000")
+    print("case: copy threads, 24 requests twice plus 4 with gaps", flush=True)
+    ctx = nls.Context(0)
+    ref = {rq.rid: nls.results_to_numpy(ctx.solve(nls.DeviceBatch(rq.batch))) for rq in requests}
+    ctx.close()
+    gapped = [(rq.rid,) + _with_gaps(rq.batch, 7, 3) for rq in requests[:4]]
+    srv = nls.Server(0, mem_budget_bytes=256 << 20, streams=4)
+    ids = {}
+    for rep in range(2):
+        for rq in requests:
+            ids[srv.submit(rq.batch)] = ("plain", rq.rid)
+    for rid, gb, u_off in gapped:
+        ids[srv.submit(gb)] = ("gaps", rid, u_off)
+    done = srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert len(done) == 2 * len(requests) + len(gapped)
+    assert st["resident_bytes"] == 0 and st["inflight_launches"] == 0
+    for info, out in done:
+        tag = ids[info["id"]]
+        assert info["status"] == 0
+        r = ref[tag[1]]
+        if tag[0] == "plain":
+            assert _same(out, r), tag
+            continue
+        b = [rq.batch for rq in requests if rq.rid == tag[1]][0]
+        u_off = tag[2]
+        for s in range(b.M):
+            assert np.array_equal(out["u"][u_off[s]:u_off[s] + b.n[s]], r["u"][b.u_off[s]:b.u_off[s + 1]])
+        gaps = np.ones(u_off[-1], bool)
+        for s in range(b.M):
+            gaps[u_off[s]:u_off[s] + b.n[s]] = False
+        assert (out["u"][gaps] == 9.0).all()
+        for k in KEYS[1:]:
+            assert np.array_equal(out[k], r[k])
