@@ -921,6 +921,9 @@ template <int NB, int L, typename TI> struct GroupShared {
   double fv[G][L];       // F at the current iterate (for J^T F)
   double dphi[G][L];     // dual derivative of the column map at the iterate
   TI piv[G][NB + 2];     // pivot row of the current elimination step + RHS
+  // zeros: the pivot row seen by the rows a step leaves as they are (the
+  // FP64 form of groups narrower than the wavefront)
+  TI zrow[G][(L < 64 && sizeof(TI) == 8) ? NB : 1];
   int ppos[G];           // the pivot row's logical position
   TI sol[G][L];          // solution of the triangular solves
   TI gv[G][L];           // g = J^T F
@@ -1247,6 +1250,10 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
   pos = own ? r : NB + 1 + r;  // logical row position; non-rows never pivot
   bool ok = true;
   myrd = TI(0);  // reciprocal of this row's pivot, once it has been the pivot row
+  if constexpr (L < 64 && sizeof(TI) == 8) {
+    // (ordered before its first read by the first step's wave_sync)
+    for (int j = r; j < NB; j += L) sh.zrow[gi][j] = TI(0);
+  }
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     if (k < n) {
@@ -1326,13 +1333,18 @@ __device__ __forceinline__ bool group_lu_solve(GroupShared<NB, L, TI>& sh, int g
         if (pos == kp) myrd = rp;
         if (pos == kp) pos = k;
         else if (pos == k) pos = kp;
-        if (own && pos > k) {
-          const TI l = J[k] * rp;
-          J[k] = l;
+        // every lane runs the update, so that the row stays in the same
+        // registers through the step: rows below the pivot row with their
+        // multiplier and the pivot row's entries, the others with a zero
+        // multiplier and the group's zero row (x + (-0 * 0) is x exactly)
+        const bool upd = own && pos > k;
+        const TI l = upd ? J[k] * rp : TI(0);
+        const TI* __restrict__ prow = upd ? &sh.piv[gi][0] : &sh.zrow[gi][0];
+        if (upd) J[k] = l;
 #pragma unroll
-          for (int j = k + 1; j < NB; ++j) J[j] = fmat(-l, sh.piv[gi][j], J[j]);
-          rhs = fmat(-l, sh.piv[gi][NB], rhs);
-        }
+        for (int j = k + 1; j < NB; ++j) J[j] = fmat(-l, prow[j], J[j]);
+        const TI er = fmat(-l, sh.piv[gi][NB], rhs);
+        rhs = upd ? er : rhs;
         wave_sync();
       }
     }

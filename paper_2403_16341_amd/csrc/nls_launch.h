@@ -73,7 +73,6 @@ struct SensArgs {
   int64_t P;
   int32_t n;
 };
-// size bucket of the sensitivity kernels: 8, 16, 24, ..., 64
 // Persistent grid under a cap of pct percent of the resident wavefronts
 // (pct <= 0 or >= 100: no cap; at least one wavefront).
 inline int grid_cap(int waves, int pct) {
@@ -82,6 +81,7 @@ inline int grid_cap(int waves, int pct) {
   return c > 0 ? c : 1;
 }
 
+// size bucket of the sensitivity kernels: 8, 16, 24, ..., 64
 inline int sens_bucket(int n) { return n <= 8 ? 8 : (n + 7) / 8 * 8; }
 int launch_sens(int nb, int fam, int mode, const SensArgs& a, hipStream_t st);
 
