@@ -53,27 +53,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SensWidth<NB
     const int64_t po = a.p_off ? a.p_off[s] : s * P;
     const double* __restrict__ p = a.params + po;
 
-    // ---- this lane's parameters, loaded up front together with u: one wait
-    // for all of them instead of one round trip per column (indices past n
-    // are clamped to a valid entry and the values dropped) ----
+    // ---- this lane's parameters and u, loaded up front with no branch: u
+    // first, so that tanh(u) needs only its own load while the rest are in
+    // flight.  Lanes without a row (and groups past the end) load a clamped
+    // valid entry and drop the value; indices past n are clamped the same way.
+    const int ne = live ? n : 1;
+    const int re = r < ne ? r : ne - 1;
+    const double ul = a.u[uo + re];
     double pa[NB];
     double beta = 0.0, br = 0.0, wr = 0.0;
     if constexpr (FAM == FAM_CUBIC || FAM == FAM_TANH) {
+      if constexpr (MODE == SENS_ADJOINT) wr = a.seed[uo + re];
+      br = p[ne * ne + re];
+      if constexpr (FAM == FAM_TANH) beta = p[ne * ne + ne];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) pa[c] = 0.0;
-      if (own) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const int cc = c < n ? c : n - 1;
-          pa[c] = MODE == SENS_TANGENT ? p[r * n + cc] : p[cc * n + r];
-        }
-        br = p[n * n + r];
-        if constexpr (FAM == FAM_TANH) beta = p[n * n + n];
-        if constexpr (MODE == SENS_ADJOINT) wr = a.seed[uo + r];
+      for (int c = 0; c < NB; ++c) {
+        const int cc = c < ne ? c : ne - 1;
+        pa[c] = MODE == SENS_TANGENT ? p[re * ne + cc] : p[cc * ne + re];
       }
     }
 
-    const double u = own ? a.u[uo + r] : 0.0;
+    const double u = own ? ul : 0.0;
     const double tu = (FAM == FAM_TANH && own) ? tanh(u) : 0.0;
     if (row) {
       xs[gi][r] = u;
