@@ -386,7 +386,12 @@ typedef struct {
 } nls_server_stats;
 
 /* Create a server: allocates the device arena and its pinned host mirror and
- * starts the scheduler thread.  Errors: NLS_E_INVALID (NULL, bad device or
+ * starts the scheduler thread and four host copy threads (a launch with more
+ * than 4 MiB of inputs or results to copy between the callers' arrays and
+ * the pinned mirror has the copies done there, in jobs of about 16 MiB, while
+ * the scheduler goes on admitting and completing others; the environment
+ * variables NLS_SERVE_INLINE_COPY_BYTES and NLS_SERVE_COPY_JOB_BYTES, read
+ * here, change the two sizes).  Errors: NLS_E_INVALID (NULL, bad device or
  * field), NLS_E_NOMEM / NLS_E_DEVICE (allocation failed).                   */
 int nls_server_create(const nls_server_desc* d, nls_server** out);
 
