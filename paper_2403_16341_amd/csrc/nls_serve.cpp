@@ -30,6 +30,7 @@
 #include <list>
 #include <memory>
 #include <mutex>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -516,8 +517,15 @@ int nls_server_create(const nls_server_desc* d, nls_server** out) {
     return sfail(e == hipErrorOutOfMemory ? NLS_E_NOMEM : NLS_E_DEVICE, m);
   }
   for (int i = max_inflight - 1; i >= 0; --i) s->free_counters.push_back(i);
-  for (int j = 0; j < kCopyThreads; ++j) s->copiers.emplace_back(copier, s);
-  s->th = std::thread(run, s);
+  try {
+    for (int j = 0; j < kCopyThreads; ++j) s->copiers.emplace_back(copier, s);
+    s->th = std::thread(run, s);
+  } catch (const std::exception& x) {
+    // (no scheduler thread yet: free_server stops and joins the copy threads)
+    const std::string m = std::string("nls_server_create: cannot start threads: ") + x.what();
+    free_server(s);
+    return sfail(NLS_E_DEVICE, m);
+  }
   *out = s;
   return NLS_OK;
 }
