@@ -352,12 +352,17 @@ def serving_leg(nls, args):
             r = ref[which[info["id"]]]
             same = same and all(np.array_equal(out[k], r[k]) for k in keys)
         sizes = np.array([i["systems"] for i, _ in infos])
+        nsz = np.array([int(pool[which[i["id"]]].batch.n[0]) for i, _ in infos])
         lat = np.array(lat)
         small = lat[sizes <= 256]
         small_queue = np.array(queue)[sizes <= 256]
+        # small requests of n <= 32: their kernels fit beside the bulk launches;
+        # those of n > 32 need a SIMD with a whole 256-register wavefront free
+        small32 = lat[(sizes <= 256) & (nsz <= 32)]
         e = {"load": frac, "rate_hz": rate, "requests": R, "wall_s": wall,
              "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": float(lat.max()),
              "p50_small_ms": _pct(small, 50), "p99_small_ms": _pct(small, 99),
+             "p99_small_n_le_32_ms": _pct(small32, 99), "max_small_n_le_32_ms": float(small32.max()) if len(small32) else None,
              "p50_queue_ms": _pct(queue, 50), "p99_queue_ms": _pct(queue, 99),
              "p99_small_queue_ms": _pct(small_queue, 99),
              "mean_merged": float(np.mean([i["merged"] for i, _ in infos])),
