@@ -95,11 +95,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SensWidth<NB
         if constexpr (FAM == FAM_CUBIC) {
           const double aij = pa[c];
           bad |= !finite64(aij);
-          v = i == j ? aij + cubic_term_deriv(xs[gi][i]) : aij;
+          // (the diagonal entry is the lane's own: its u is in a register)
+          v = i == j ? aij + cubic_term_deriv(u) : aij;
         } else if constexpr (FAM == FAM_TANH) {
           const double aij = pa[c];
           bad |= !finite64(aij);
-          const double w = aij * dtanh_known(dseed(xs[gi][j]), ts[gi][j]).d;
+          // adjoint: column j = r is the lane's own, tanh'(u_r) from registers
+          const double w = aij * (MODE == SENS_ADJOINT ? dtanh_known(dseed(u), tu).d
+                                                       : dtanh_known(dseed(xs[gi][j]), ts[gi][j]).d);
           v = i == j ? w + beta : w;
         } else if constexpr (FAM == FAM_ROSENBROCK) {
           if (i == 0) {
