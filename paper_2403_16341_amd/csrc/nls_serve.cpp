@@ -193,10 +193,9 @@ bool run_copies(nls_server* s, InFlight& L, size_t (*bytes_per_system)(const Req
   std::vector<std::function<void()>> jobs;
   for (size_t j = 0; j < L.reqs.size(); ++j) {
     const Req& q = L.reqs[j];
-    const int64_t step = std::max<int64_t>(1, (int64_t)(s->copy_job_bytes / bytes_per_system(q)));
     const int64_t first = L.plan.first[j];
-    for (int64_t i0 = 0; i0 < q.M; i0 += step) {
-      const int64_t i1 = std::min<int64_t>(q.M, i0 + step);
+    for (const auto& rg : copy_ranges(q.M, bytes_per_system(q), s->copy_job_bytes)) {
+      const int64_t i0 = rg.first, i1 = rg.second;
       InFlight* lp = &L;
       const Req* qp = &q;
       jobs.push_back([s, lp, qp, first, i0, i1, copy] {

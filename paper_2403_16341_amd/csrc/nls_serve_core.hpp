@@ -12,6 +12,7 @@
 #include <iterator>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace nls {
@@ -231,6 +232,16 @@ inline int64_t slice_systems(int n, double slice_work) {
 }
 
 inline double launch_work(int64_t m, int n) { return (double)m * n * n * n; }
+
+// Host copy jobs of a request of m systems at bytes_per_system each: ranges
+// [i0, i1) that cover 0 .. m - 1 in order, each of at most job_bytes (at least
+// one system per range).
+inline std::vector<std::pair<int64_t, int64_t>> copy_ranges(int64_t m, size_t bytes_per_system, size_t job_bytes) {
+  std::vector<std::pair<int64_t, int64_t>> r;
+  const int64_t step = std::max<int64_t>(1, (int64_t)(job_bytes / (bytes_per_system ? bytes_per_system : 1)));
+  for (int64_t i0 = 0; i0 < m; i0 += step) r.emplace_back(i0, std::min<int64_t>(m, i0 + step));
+  return r;
+}
 
 // Launches up to this much work (systems x n^3; e.g. 16k systems at n = 16,
 // 256 at n = 64) may use stream 0; larger ones never do.

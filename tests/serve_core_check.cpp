@@ -286,7 +286,27 @@ static void check_slices_and_streams() {
   CHECK(pick_stream(one, kExpressWork * 2) == 0, "a single stream takes everything");
 }
 
+// copy jobs: ordered ranges that partition the systems, each within the
+// job size unless a single system exceeds it
+static void check_copy_ranges() {
+  for (int64_t m : {int64_t(0), int64_t(1), int64_t(7), int64_t(1000), int64_t(65536)}) {
+    for (size_t bps : {size_t(1), size_t(24), size_t(2304), size_t(33288)}) {
+      for (size_t job : {size_t(1), size_t(3000), size_t(16) << 20}) {
+        const auto r = copy_ranges(m, bps, job);
+        int64_t at = 0;
+        for (const auto& x : r) {
+          CHECK(x.first == at && x.second > x.first, "m=%lld: ranges in order, non-empty", (long long)m);
+          CHECK((size_t)(x.second - x.first) * bps <= job || x.second - x.first == 1, "range within the job size");
+          at = x.second;
+        }
+        CHECK(at == m, "m=%lld bps=%zu job=%zu: ranges cover every system", (long long)m, bps, job);
+      }
+    }
+  }
+}
+
 int main() {
+  check_copy_ranges();
   check_chain_layout();
   check_slices_and_streams();
   check_arena();
